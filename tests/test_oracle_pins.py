@@ -1,0 +1,518 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test states the passage it checks and the kind of mistake it would catch.
+None of them calls the HIP library.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import workloads as W
+from conftest import golden
+from helpers import derived, params, pool_case
+from oracle import eos, orc
+
+GOLD = golden("paper_values.txt")
+EX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+EY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+WL = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+
+def base_abR():
+    P = W.BASE_PARAMS
+    return P["a"], P["b"], P["R"], P["omega"]
+
+
+# ---------------------------------------------------------------- EOS (Eq. 13)
+def test_printed_constants_match_inputs():
+    """The base parameter set carries the printed values of Sections 2.1 and 3.1."""
+    P = W.BASE_PARAMS
+    for key, gk in [("a", "a_printed"), ("b", "b_printed"), ("R", "R_printed"), ("omega", "omega_printed"),
+                    ("Cv", "Cv_printed"), ("Cvchi", "Cvchi_printed"), ("lambda_S", "lambda_S_printed"),
+                    ("g", "g_printed")]:
+        assert P[key] == pytest.approx(GOLD[gk][0], rel=1e-12), key
+    # Eq. 4: tau = nu / c_s^2 + 0.5
+    assert P["tau_L"] == pytest.approx(GOLD["nu_L_printed"][0] * 3 + 0.5, rel=1e-12)
+    assert P["tau_V"] == pytest.approx(GOLD["nu_V_printed"][0] * 3 + 0.5, rel=1e-12)
+
+
+def test_tc_formula_reproduces_printed_tc_for_a_3_49():
+    """Section 2.1: Tc from a = 0.45724 R^2 Tc^2/Pc, b = 0.0778 R Tc/Pc.  The
+    printed Tc = 0.1094 follows for a = 3/49 (the printed a = 2/49 gives 0.0729)."""
+    val, tol, _ = GOLD["Tc_printed"]
+    assert abs(eos.critical_temperature(3 / 49, 2 / 21, 1.0) - val) <= tol
+    assert eos.critical_temperature(2 / 49, 2 / 21, 1.0) == pytest.approx(0.0729220, abs=1e-7)
+
+
+@pytest.mark.parametrize("a", [2 / 49, 3 / 49])
+def test_numeric_critical_point_matches_formula(a):
+    """The Tc formula is the critical point of Eq. 13: at T = Tc the isotherm
+    has an inflection with zero slope.  Found here by bisection on the sign of
+    min_rho dP/drho (numerical differences), independent of the formula."""
+    _, b, R, om = base_abR()
+    Tcf = eos.critical_temperature(a, b, R)
+
+    def min_slope(T):
+        rho = np.linspace(0.5, 6.0, 4001)
+        P = np.array([eos.pressure(r, T, a, b, R, om, Tcf) for r in rho])
+        return np.min(np.diff(P) / np.diff(rho))
+
+    lo, hi = 0.95 * Tcf, 1.05 * Tcf
+    for _ in range(50):
+        mid = 0.5 * (lo + hi)
+        if min_slope(mid) < 0:
+            lo = mid
+        else:
+            hi = mid
+    assert 0.5 * (lo + hi) == pytest.approx(Tcf, rel=2e-4)
+
+
+@pytest.mark.parametrize("a", [2 / 49, 3 / 49])
+def test_maxwell_pair_matches_printed_densities(a):
+    """Section 3.1: rho_L = 6.5 and rho_V = 0.38 at T_sat = 0.86 Tc by Maxwell
+    construction (they do not depend on a).  The equal-area rule is re-checked
+    with adaptive quadrature of P over v, independent of the closed-form
+    antiderivative the oracle uses."""
+    _, b, R, om = base_abR()
+    Tc = eos.critical_temperature(a, b, R)
+    T = GOLD["Tsat_over_Tc"][0] * Tc
+    rl, rv, ps = eos.maxwell(T, a, b, R, om, Tc)
+    for v, key in [(rl, "rho_L_printed"), (rv, "rho_V_printed")]:
+        val, tol, _ = GOLD[key]
+        assert abs(v - val) <= tol, (key, v)
+    P = lambda r: eos.pressure(r, T, a, b, R, om, Tc)
+    assert P(rl) == pytest.approx(ps, rel=1e-10)
+    assert P(rv) == pytest.approx(ps, rel=1e-10)
+    area, _ = integrate.quad(lambda v: P(1.0 / v), 1.0 / rl, 1.0 / rv, epsabs=1e-14, epsrel=1e-12, limit=200)
+    assert area == pytest.approx(ps * (1.0 / rv - 1.0 / rl), rel=1e-9)
+
+
+def test_latent_heat_clapeyron_and_printed_value():
+    """Section 3.1 prints h_LV = 0.58.  The oracle's T*(s_V - s_L) from the
+    Maxwell relation (Eq. 19) must equal the Clausius-Clapeyron value
+    T (v_V - v_L) dP_sat/dT with dP_sat/dT from finite differences of the
+    Maxwell saturation pressure; with a = 3/49 it rounds to the printed value."""
+    _, b, R, om = base_abR()
+    for a in (2 / 49, 3 / 49):
+        Tc = eos.critical_temperature(a, b, R)
+        T = 0.86 * Tc
+        h = eos.latent_heat(T, a, b, R, om, Tc)
+        dT = 1e-5 * Tc
+        p_hi = eos.maxwell(T + dT, a, b, R, om, Tc)[2]
+        p_lo = eos.maxwell(T - dT, a, b, R, om, Tc)[2]
+        rl, rv, _ = eos.maxwell(T, a, b, R, om, Tc)
+        h_cc = T * (1 / rv - 1 / rl) * (p_hi - p_lo) / (2 * dT)
+        assert h == pytest.approx(h_cc, rel=1e-6)
+    assert abs(round(eos.latent_heat(0.86 * eos.critical_temperature(3 / 49, b, R), 3 / 49, b, R, om,
+                                     eos.critical_temperature(3 / 49, b, R)), 2) - GOLD["h_LV_printed"][0]) < 0.011
+
+
+def test_property_ratios_printed():
+    """Section 3.1: mu_L/mu_V ~ 10, lambda_L/lambda_V ~ 17, lambda_S/lambda_L ~ 50,
+    with mu = rho nu and lambda = C_V chi rho in the fluid."""
+    d = derived(*base_abR())
+    P = W.BASE_PARAMS
+    mu = d["rho_L"] * GOLD["nu_L_printed"][0] / (d["rho_V"] * GOLD["nu_V_printed"][0])
+    lam_lv = (P["Cvchi"] * d["rho_L"]) / (P["Cvchi"] * d["rho_V"])
+    lam_sl = P["lambda_S"] / (P["Cvchi"] * d["rho_L"])
+    for v, key in [(mu, "mu_ratio_printed"), (lam_lv, "lam_ratio_LV"), (lam_sl, "lam_ratio_SL")]:
+        val, tol, _ = GOLD[key]
+        assert abs(v - val) <= tol + 0.5, (key, v)
+
+
+def test_c_oracle_eos_and_dpdt(oracle_lib):
+    """Eq. 13 in the C oracle equals the Python one, and its hand-derived
+    (dP/dT)_rho matches a central difference of P (catches a sign or factor
+    slip in the derivative used by the latent-heat term of Eq. 24)."""
+    P, d = params(8, 8, 4)
+    p = orc.make_params(**P)
+    a, b, R, om = P["a"], P["b"], P["R"], P["omega"]
+    for rho in (0.2, 0.38, 1.5, 2.6, 4.0, 6.5, 7.5):
+        for T in (0.7 * d["Tc"], d["Tsat"], 0.95 * d["Tc"], 1.2 * d["Tc"]):
+            assert orc.pressure(p, rho, T) == pytest.approx(eos.pressure(rho, T, a, b, R, om, d["Tc"]), rel=1e-13)
+            h = 1e-6 * T
+            fd = (orc.pressure(p, rho, T + h) - orc.pressure(p, rho, T - h)) / (2 * h)
+            assert orc.dpdt(p, rho, T) == pytest.approx(fd, rel=1e-7, abs=1e-12)
+    # Eq. 12 with G = -1: psi^2 = 2 (rho/3 - P)
+    ps, rad = orc.psi(p, d["rho_L"], d["Tsat"])
+    assert ps * ps == pytest.approx(2 * (d["rho_L"] / 3 - eos.pressure(d["rho_L"], d["Tsat"], a, b, R, om, d["Tc"])),
+                                    rel=1e-12)
+
+
+# ------------------------------------------------------ MRT collision (Eqs. 6-9)
+def test_moment_matrix_orthogonal_and_equilibrium(oracle_lib):
+    """Eq. 6: M is orthogonal with M M^T = diag(9,36,36,6,12,6,12,4,4), and
+    M applied to the textbook second-order D2Q9 equilibrium gives m^eq."""
+    M = orc.moment_matrix()
+    np.testing.assert_array_equal(M @ M.T, np.diag([9, 36, 36, 6, 12, 6, 12, 4, 4]).astype(float))
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        rho = rng.uniform(0.3, 7.0)
+        ux, uy = rng.uniform(-0.1, 0.1, 2)
+        eu = EX * ux + EY * uy
+        feq = WL * rho * (1 + 3 * eu + 4.5 * eu ** 2 - 1.5 * (ux * ux + uy * uy))
+        u2 = ux * ux + uy * uy
+        meq = rho * np.array([1, -2 + 3 * u2, 1 - 3 * u2, ux, -ux, uy, -uy, ux * ux - uy * uy, ux * uy])
+        np.testing.assert_allclose(M @ feq, meq, rtol=0, atol=1e-14 * rho)
+
+
+def test_collision_reduces_to_bgk_with_guo_forcing(oracle_lib):
+    """Special case: all rates 1/tau (s_e = s_q = s_nu) and varpi = 0 make Eq. 7
+    with the forcing of Eq. 9 equal single-relaxation BGK with the standard
+    (Guo) forcing term F_i = (1 - 1/(2 tau)) w_i [3(e_i - u) + 9 (e_i.u) e_i].F.
+    Catches any wrong entry of M, m^eq, the rows of Eq. 9 (including the
+    reading u_x F_y + u_y F_x of row 8), the (I - Lambda/2) factor or M^{-1}."""
+    rng = np.random.default_rng(2)
+    for tau in (0.7, 0.8, 1.0, 1.3):
+        P, _ = params(4, 4, 4, varpi=0.0, s_e=1 / tau, s_q=1 / tau, tau_L=tau, tau_V=tau)
+        p = orc.make_params(**P)
+        for _ in range(10):
+            rho = rng.uniform(0.3, 7.0)
+            f = WL * rho * (1 + rng.uniform(-0.2, 0.2, 9))
+            rho = f.sum()
+            F = rng.uniform(-0.05, 0.05, 2)
+            Fm = rng.uniform(-0.05, 0.05, 2)
+            ux = ((EX * f).sum() + F[0] / 2) / rho
+            uy = ((EY * f).sum() + F[1] / 2) / rho
+            out = orc.collide_node(p, f, rho, ux, uy, F[0], F[1], Fm[0], Fm[1], 1.3)
+            eu = EX * ux + EY * uy
+            feq = WL * rho * (1 + 3 * eu + 4.5 * eu ** 2 - 1.5 * (ux * ux + uy * uy))
+            guo = (1 - 0.5 / tau) * WL * (3 * ((EX - ux) * F[0] + (EY - uy) * F[1]) + 9 * eu * (EX * F[0] + EY * F[1]))
+            ref = f - (f - feq) / tau + guo
+            np.testing.assert_allclose(out, ref, rtol=0, atol=2e-15 * rho)
+
+
+def test_varpi_term_moment_rows(oracle_lib):
+    """Eq. 9 thermodynamic-consistency term: it changes only moments 1 and 2 of
+    f*, by +c and -c (the minus is this build's reading for row 2) with
+    c = (1 - s_e/2) 12 varpi |F_m|^2 / (psi^2 (1/s_e - 1/2)) = 12 varpi s_e |F_m|^2 / psi^2."""
+    M = orc.moment_matrix()
+    rng = np.random.default_rng(3)
+    for se in (0.6, 0.8, 1.2):
+        P1, _ = params(4, 4, 4, varpi=0.1, s_e=se)
+        P0, _ = params(4, 4, 4, varpi=0.0, s_e=se)
+        for _ in range(5):
+            f = WL * 3.0 * (1 + rng.uniform(-0.1, 0.1, 9))
+            rho = f.sum()
+            F, Fm = rng.uniform(-0.05, 0.05, 2), rng.uniform(-0.05, 0.05, 2)
+            ux, uy = ((EX * f).sum() + F[0] / 2) / rho, ((EY * f).sum() + F[1] / 2) / rho
+            psi = rng.uniform(0.4, 2.1)
+            a1 = orc.collide_node(orc.make_params(**P1), f, rho, ux, uy, *F, *Fm, psi)
+            a0 = orc.collide_node(orc.make_params(**P0), f, rho, ux, uy, *F, *Fm, psi)
+            dm = M @ (a1 - a0)
+            c = 12 * 0.1 * se * (Fm @ Fm) / psi ** 2
+            np.testing.assert_allclose(dm, [0, c, -c, 0, 0, 0, 0, 0, 0], rtol=0, atol=1e-14 + 1e-9 * c)
+
+
+def test_collision_conserves_mass_and_adds_force(oracle_lib):
+    """Eqs. 7 and 10: sum f* = rho exactly and sum e f* = j + F for any s_j."""
+    rng = np.random.default_rng(4)
+    P, _ = params(4, 4, 4)
+    p = orc.make_params(**P)
+    for _ in range(20):
+        f = WL * rng.uniform(0.3, 7.0) * (1 + rng.uniform(-0.3, 0.3, 9))
+        rho = f.sum()
+        F, Fm = rng.uniform(-0.05, 0.05, 2), rng.uniform(-0.05, 0.05, 2)
+        jx, jy = (EX * f).sum(), (EY * f).sum()
+        out = orc.collide_node(p, f, rho, (jx + F[0] / 2) / rho, (jy + F[1] / 2) / rho, *F, *Fm, 1.0)
+        assert out.sum() == pytest.approx(rho, rel=1e-14)
+        assert (EX * out).sum() == pytest.approx(jx + F[0], abs=1e-14 * rho)
+        assert (EY * out).sum() == pytest.approx(jy + F[1], abs=1e-14 * rho)
+
+
+# ------------------------------------------------------------- forces (Eqs. 11-15)
+def test_forces_on_a_layered_field(oracle_lib):
+    """For an x-uniform field the sums of Eqs. 11 and 14 collapse (w(1) + 2 w(2) = 1/2):
+    F_my(y) = psi(y) (psi(y+1) - psi(y-1)) / 2 in the bulk, the bottom fluid row sees
+    psi(0) (psi(1) + gamma) / 2 and the top row psi(top) (gamma - psi(top-1)) / 2,
+    F_x = 0, and F_y - F_my - F_ads,y = -(rho - rho_bar) g (Eq. 15)."""
+    nx, nyf = 6, 24
+    P, d, bc, rho, T = pool_case(nx, nyf, 4, n_spots=0)
+    rho = W.slab_rho(nx, nyf, 6.0, 14.0, d["rho_L"], d["rho_V"], width=3.0)
+    gam = -0.55 * d["psi_L"]
+    dom = orc.Domain(**P)
+    dom.set_bc(d["Tsat"], np.full(nx, d["Tsat"]), gamma_bot=np.full(nx, gam), gamma_top=np.full(nx, gam))
+    dom.set_fields(rho, np.full((nyf + 4, nx), d["Tsat"]))
+    Fo = dom.read_forces()
+    psi = Fo["psi"][:, 0]
+    Fmy = Fo["Fmy"][:, 0]
+    exp = np.empty(nyf)
+    exp[1:-1] = psi[1:-1] * (psi[2:] - psi[:-2]) / 2
+    exp[0] = psi[0] * psi[1] / 2
+    exp[-1] = -psi[-1] * psi[-2] / 2
+    np.testing.assert_allclose(Fmy, exp, rtol=1e-13, atol=1e-15)
+    np.testing.assert_array_equal(Fo["Fmx"], 0.0)
+    Fads = Fo["Fy"][:, 0] - Fmy + (rho[:, 0] - dom.rho_bar) * P["g"]
+    exp_ads = np.zeros(nyf)
+    exp_ads[0] = psi[0] * gam / 2
+    exp_ads[-1] = -psi[-1] * gam / 2
+    np.testing.assert_allclose(Fads, exp_ads, rtol=1e-12, atol=1e-15)
+    assert dom.rho_bar == pytest.approx(rho.mean(), rel=1e-14)
+
+
+def test_forces_on_a_field_layered_in_x(oracle_lib):
+    """Same collapse along x on a periodic box: a y-uniform field gives
+    F_mx(x) = psi(x) (psi(x+1) - psi(x-1)) / 2 (periodic) and F_my = 0."""
+    nx, ny = 30, 4
+    P, d = params(nx, ny, 0, periodic_y=1, isothermal=1)
+    rho = np.ascontiguousarray(W.slab_rho(ny, nx, 8.0, 20.0, d["rho_L"], d["rho_V"], width=3.0).T)
+    dom = orc.Domain(**P)
+    dom.set_bc(d["Tsat"])
+    dom.set_fields(rho, np.full((ny, nx), d["Tsat"]))
+    Fo = dom.read_forces()
+    psi = Fo["psi"][0]
+    exp = psi * (np.roll(psi, -1) - np.roll(psi, 1)) / 2
+    np.testing.assert_allclose(Fo["Fmx"][0], exp, rtol=1e-13, atol=1e-15)
+    assert np.abs(Fo["Fmy"]).max() < 1e-15
+
+
+def test_total_momentum_conserved_on_periodic_domain(oracle_lib):
+    """Eq. 11 is a pair force (equal and opposite on each link) and sum (rho -
+    rho_bar) g = 0, so on a fully periodic domain the total momentum sum e f
+    is constant to round-off; mass too.  Catches a wrong neighbour index or an
+    asymmetric weight in the force or the streaming."""
+    nx, ny = 24, 20
+    P, d = params(nx, ny, 0, periodic_y=1, isothermal=1)
+    rho = W.perturbed(W.drop_rho(nx, ny, 6.0, d["rho_L"], d["rho_V"], width=3.0, cx=10.3, cy=8.7), 0.01, 5)
+    dom = orc.Domain(**P)
+    dom.set_bc(d["Tsat"])
+    dom.set_fields(rho, np.full((ny, nx), d["Tsat"]))
+    f0 = dom.read()["f"]
+    m0, jx0, jy0 = f0.sum(), (EX[:, None, None] * f0).sum(), (EY[:, None, None] * f0).sum()
+    assert dom.step(200) == 0
+    f1 = dom.read()["f"]
+    assert f1.sum() == pytest.approx(m0, rel=1e-13)
+    assert abs((EX[:, None, None] * f1).sum() - jx0) < 1e-11
+    assert abs((EY[:, None, None] * f1).sum() - jy0) < 1e-11
+
+
+def test_mass_conserved_with_walls_and_heater(oracle_lib):
+    """Halfway bounce-back and periodic x conserve mass exactly (Eq. 8 with
+    the wall rule): total mass after 200 boiling steps equals the initial one."""
+    P, d, bc, rho, T = pool_case(30, 30, 4, superheat=0.15)
+    dom = orc.Domain(**P)
+    dom.set_bc(**bc)
+    dom.set_fields(rho, T)
+    m0 = rho.sum()
+    assert dom.step(200) == 0
+    assert dom.read()["rho"].sum() == pytest.approx(m0, rel=1e-13)
+
+
+def test_rest_state_is_stationary(oracle_lib):
+    """Uniform density and temperature, no gravity, walls with the neutral
+    adhesion gamma = -psi(rho): every force vanishes, f = w rho is a fixed point
+    of collision and bounce-back, and T does not move."""
+    nx, nyf, nys = 7, 9, 4
+    P, d = params(nx, nyf, nys, g=0.0)
+    rho0 = 0.5 * (d["rho_L"] + d["rho_V"]) * 0 + d["rho_L"]
+    dom = orc.Domain(**P)
+    gam = np.full(nx, -d["psi_L"])
+    dom.set_bc(d["Tsat"], np.full(nx, d["Tsat"]), gamma_bot=gam, gamma_top=gam)
+    dom.set_fields(np.full((nyf, nx), rho0), np.full((nyf + nys, nx), d["Tsat"]))
+    f0 = dom.read()["f"]
+    assert dom.step(50) == 0
+    r = dom.read()
+    np.testing.assert_allclose(r["f"], f0, rtol=1e-13)
+    np.testing.assert_allclose(r["T"], d["Tsat"], rtol=1e-14)
+    assert np.abs(r["ux"]).max() < 1e-14 and np.abs(r["uy"]).max() < 1e-14
+
+
+def test_mirror_symmetry(oracle_lib):
+    """An x-mirror-symmetric start (about x = (nx-1)/2) stays symmetric: rho, T
+    and u_y even, u_x odd.  Catches a wrong velocity ordering or sign in e."""
+    nx, nyf, nys = 20, 24, 4
+    P, d, bc, rho, T = pool_case(nx, nyf, nys, n_spots=0, superheat=0.2)
+    Tb = np.full(nx, d["Tsat"] + 0.2 * d["Tc"])
+    Tb[3:6] *= 1.02
+    Tb[nx - 6:nx - 3] *= 1.02
+    rho = rho.copy()
+    rho[9:11, 8:12] = d["rho_V"]
+    T[0] = Tb
+    dom = orc.Domain(**P)
+    dom.set_bc(d["Tsat"], Tb, gamma_bot=bc["gamma_bot"], gamma_top=bc["gamma_top"])
+    dom.set_fields(rho, T)
+    assert dom.step(150) == 0
+    r = dom.read()
+    for k, sgn in [("rho", 1), ("T", 1), ("uy", 1), ("ux", -1)]:
+        a = r[k]
+        np.testing.assert_allclose(a, sgn * a[:, ::-1], rtol=0, atol=1e-12 * np.abs(a).max())
+
+
+# ----------------------------------------------------- energy equation (Eqs. 24-28)
+def _fourier_symbol(kx, ky):
+    return 6.0 * np.sum(WL[1:] * (np.cos(kx * EX[1:] + ky * EY[1:]) - 1.0))
+
+
+def test_thermal_stencils_on_fourier_modes(oracle_lib):
+    """Eqs. 27-28 with the lattice weights: on T = T0 + eps cos(k.x) and uniform
+    rho, v, K of Eq. 24 is  alpha * 6 sum w (cos(k.e) - 1) * eps cos(k.x)  (diffusion,
+    alpha = C_V chi / C_V)  minus  v . grad T with the discrete gradient
+    3 sum w e sin-shift = eps k-symbol; all closed forms."""
+    nx, ny = 16, 12
+    P, d = params(nx, ny, 0, periodic_y=1)
+    dom = orc.Domain(**P)
+    dom.set_bc(d["Tsat"])
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    kx, ky = 2 * np.pi * 3 / nx, 2 * np.pi * 2 / ny
+    eps, T0 = 1e-3, d["Tsat"]
+    Tf = T0 + eps * np.cos(kx * x + ky * y)
+    rho = np.full((ny, nx), 2.0)
+    Ux, Uy = 0.013, -0.021
+    K = dom.thermal_rhs(Tf, rho, np.full((ny, nx), Ux), np.full((ny, nx), Uy))
+    alpha = P["Cvchi"] / P["Cv"]
+    # discrete gradient of cos(k.x + phase): 3 sum w e cos(k.(x+e)) = -sin(k.x) * 3 sum w e sin(k.e)
+    gxs = 3 * np.sum(WL * EX * np.sin(kx * EX + ky * EY))
+    gys = 3 * np.sum(WL * EY * np.sin(kx * EX + ky * EY))
+    ph = kx * x + ky * y
+    exp = alpha * _fourier_symbol(kx, ky) * eps * np.cos(ph) - (Ux * (-gxs) + Uy * (-gys)) * eps * np.sin(ph)
+    np.testing.assert_allclose(K, exp, rtol=0, atol=1e-14)
+    # the gradient symbol reduces to sin(k) along an axis
+    assert 3 * np.sum(WL * EX * np.sin(kx * EX)) == pytest.approx(np.sin(kx), rel=1e-14)
+
+
+def test_latent_heat_term(oracle_lib):
+    """Eq. 24 source -T/(rho C_V) (dP/dT)_rho div v: with uniform T, rho and
+    v = (A sin(k x), 0) the discrete divergence is A cos(k x) sin(k); (dP/dT)
+    is taken here from a central difference of the Python EOS."""
+    nx, ny = 20, 6
+    P, d = params(nx, ny, 0, periodic_y=1)
+    dom = orc.Domain(**P)
+    dom.set_bc(d["Tsat"])
+    x = np.arange(nx, dtype=float)[None, :] * np.ones((ny, 1))
+    k, A = 2 * np.pi * 2 / nx, 0.01
+    for rho0 in (d["rho_V"], 2.5, d["rho_L"]):
+        T0 = d["Tsat"]
+        K = dom.thermal_rhs(np.full((ny, nx), T0), np.full((ny, nx), rho0), A * np.sin(k * x), np.zeros((ny, nx)))
+        h = 1e-6 * T0
+        args = (P["a"], P["b"], P["R"], P["omega"], d["Tc"])
+        dpdt_fd = (eos.pressure(rho0, T0 + h, *args) - eos.pressure(rho0, T0 - h, *args)) / (2 * h)
+        exp = -T0 / (rho0 * P["Cv"]) * dpdt_fd * A * np.cos(k * x) * np.sin(k)
+        np.testing.assert_allclose(K, exp, rtol=1e-7, atol=1e-18)
+
+
+@pytest.mark.parametrize("m", [(1, 0), (2, 1), (3, 3)])
+def test_rk4_fourier_decay(oracle_lib, m):
+    """Eqs. 25-26: for pure conduction a Fourier mode is multiplied per step by
+    R(z) = 1 + z + z^2/2 + z^3/6 + z^4/24 with z the symbol of Eq. 28 times
+    alpha.  Exact for the discrete scheme, so it pins the RK4 stage weights."""
+    nx, ny, n = 12, 10, 40
+    P, d = params(nx, ny, 0, periodic_y=1, frozen_flow=1)
+    dom = orc.Domain(**P)
+    dom.set_bc(d["Tsat"])
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    kx, ky = 2 * np.pi * m[0] / nx, 2 * np.pi * m[1] / ny
+    eps, T0 = 2e-3, d["Tsat"]
+    dom.set_fields(np.full((ny, nx), 1.7), T0 + eps * np.cos(kx * x + ky * y))
+    dom.step(n)
+    z = P["Cvchi"] / P["Cv"] * _fourier_symbol(kx, ky)
+    Rz = 1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24
+    np.testing.assert_allclose(dom.read()["T"] - T0, eps * Rz ** n * np.cos(kx * x + ky * y), rtol=0, atol=1e-15)
+
+
+def test_steady_conduction_through_heater_and_liquid(oracle_lib):
+    """Steady 1-D conduction (frozen liquid over the heater): the heat flux is
+    the same on every row link, so T is piecewise linear with link resistances
+    1/lambda_S in the heater, the harmonic mean at the interface, 1/lambda_L in
+    the liquid and 1/lambda_L on the link to the T_sat row.  Eq. 36 at the
+    heater bottom and the interface link flux both equal that flux."""
+    nx, nyf, nys = 3, 4, 6
+    P, d = params(nx, nyf, nys, frozen_flow=1)
+    lamL = P["Cvchi"] * d["rho_L"]
+    lamS = P["lambda_S"]
+    Tb, Tt = d["Tsat"] + 0.1 * d["Tc"], d["Tsat"]
+    dom = orc.Domain(**P)
+    dom.set_bc(Tt, np.full(nx, Tb))
+    dom.set_fields(np.full((nyf, nx), d["rho_L"]), W.thermal_init(nx, nys, nyf, Tt, np.full(nx, Tb)))
+    dom.step(60000)
+    dom.flux_window(dom.t + 1, dom.t + 2, 1)
+    dom.step(1)
+    res = [1 / lamS] * (nys - 1) + [(lamS + lamL) / (2 * lamS * lamL)] + [1 / lamL] * (nyf - 1) + [1 / lamL]
+    q = (Tb - Tt) / sum(res)
+    prof = Tb - q * np.concatenate([[0.0], np.cumsum(res)])[: nys + nyf]
+    np.testing.assert_allclose(dom.read()["T"][:, 0], prof, rtol=1e-11)
+    hf = dom.heat_flux()
+    assert hf["q_bottom_inst"] == pytest.approx(q, rel=1e-9)
+    assert hf["q_top_inst"] == pytest.approx(q, rel=1e-9)
+    assert hf["T_w_inst"] == pytest.approx(prof[nys - 1], rel=1e-12)
+
+
+def test_bottom_temperature_window(oracle_lib):
+    """Section 3.2 trigger: the alternative heater-bottom row is active for
+    t0 <= t < t1 and the base row outside; Dirichlet row 0 holds T_b(x, t)."""
+    nx, nyf, nys = 8, 6, 3
+    P, d = params(nx, nyf, nys, frozen_flow=1)
+    base = np.full(nx, d["Tsat"] + 0.05 * d["Tc"])
+    alt = W.sinus_Tb(nx, base[0], 0.02 * d["Tc"], 8.0)
+    dom = orc.Domain(**P)
+    dom.set_bc(d["Tsat"], base, Tb_alt=alt, t0=3, t1=6)
+    dom.set_fields(np.full((nyf, nx), d["rho_L"]), W.thermal_init(nx, nys, nyf, d["Tsat"], base))
+    for t in range(1, 9):
+        dom.step(1)
+        exp = alt if 3 <= t < 6 else base
+        np.testing.assert_array_equal(dom.read()["T"][0], exp)
+
+
+def test_checkpoint_resume_is_exact(oracle_lib):
+    """Restarting from (f(t), T(t), t, rho_bar) reproduces the uninterrupted run bit for bit."""
+    P, d, bc, rho, T = pool_case(16, 20, 4, superheat=0.2)
+    a = orc.Domain(**P)
+    a.set_bc(**bc)
+    a.set_fields(rho, T)
+    a.step(30)
+    s = a.read()
+    a.step(30)
+    b = orc.Domain(**P)
+    b.set_bc(**bc)
+    b.set_state(s["f"], s["T"], 30, a.rho_bar)
+    b.step(30)
+    ra, rb = a.read(), b.read()
+    for k in ("f", "T", "rho", "ux", "uy"):
+        np.testing.assert_array_equal(ra[k], rb[k])
+
+
+# ------------------------------------------------------------ physical pins (slow-ish)
+def test_flat_interface_coexistence(oracle_lib):
+    """Section 3.1: a flat liquid slab at T_sat relaxes to bulk densities close
+    to the Maxwell pair (the varpi term of Eq. 9 exists to achieve this).
+    Tolerance: 3% on rho_L, 15% on rho_V (uncalibrated varpi)."""
+    nx, ny = 2, 80
+    P, d = params(nx, ny, 0, periodic_y=1, isothermal=1)
+    dom = orc.Domain(**P)
+    dom.set_bc(d["Tsat"])
+    dom.set_fields(W.slab_rho(nx, ny, 20.0, 60.0, d["rho_L"], d["rho_V"], width=4.0), np.full((ny, nx), d["Tsat"]))
+    assert dom.step(15000) == 0
+    rho = dom.read()["rho"][:, 0]
+    assert rho[40] == pytest.approx(d["rho_L"], rel=0.03)
+    assert rho[0] == pytest.approx(d["rho_V"], rel=0.15)
+
+
+@pytest.mark.slow
+def test_laplace_law(oracle_lib):
+    """Section 3.1 (surface tension from Laplace's law): static drops in a
+    periodic box obey dp = sigma / R; dp from Eq. 13 inside/outside is linear in
+    1/R with a small intercept, and sigma > 0."""
+    n = 64
+    P, d = params(n, n, 0, periodic_y=1, isothermal=1, g=0.0)
+    args = (P["a"], P["b"], P["R"], P["omega"], d["Tc"])
+    inv_r, dps = [], []
+    for R0 in (10.0, 14.0, 18.0):
+        dom = orc.Domain(**P)
+        dom.set_bc(d["Tsat"])
+        dom.set_fields(W.drop_rho(n, n, R0, d["rho_L"], d["rho_V"], width=4.0), np.full((n, n), d["Tsat"]))
+        assert dom.step(3000) == 0
+        rho = dom.read()["rho"]
+        c = n // 2
+        rin, rout = rho[c, c], rho[0, 0]
+        mid = 0.5 * (rin + rout)
+        row = rho[c, c:]
+        k = int(np.argmax(row < mid))
+        radius = (k - 1) + (row[k - 1] - mid) / (row[k - 1] - row[k]) + 0.5
+        inv_r.append(1.0 / radius)
+        dps.append(eos.pressure(rin, d["Tsat"], *args) - eos.pressure(rout, d["Tsat"], *args))
+    slope, icpt = np.polyfit(inv_r, dps, 1)
+    assert slope > 0
+    fit = slope * np.array(inv_r) + icpt
+    assert np.max(np.abs(fit - dps)) < 0.05 * max(dps)
+    assert abs(icpt) < 0.15 * max(dps)
