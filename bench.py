@@ -1,0 +1,166 @@
+#!/usr/bin/env python
+"""Benchmark of the pool-boiling LBM step on one MI355X.
+
+Default workload: the roofline case, a 4096x2048 fluid domain over a 4096x64
+heater, FP32-deviation population storage with FP64 arithmetic (EOS, T, rho),
+one +2% hot spot per 64 heater columns (seed 0), heater-bottom superheat
+0.1 Tc, heat flux sampled every 10 steps.  A step is one full time step of the
+method (flow launch + thermal launch [+ flux sample]).  Inputs are resident in
+HBM when the timed region starts.
+
+Prints ONE JSON line with MLUPS (fluid-node updates per second), the roofline
+of the step against the 8 TB/s HBM peak and the FP64 oracle timed on the host
+on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (nx, nyf, nys, precision, description)
+    "roofline": (4096, 2048, 64, 1, "pool boiling 4096x2048 fluid + 4096x64 heater, FP32-deviation populations, "
+                                    "FP64 EOS/T/rho, 1 hot spot per 64 columns, superheat 0.1 Tc"),
+    "roofline_fp64": (4096, 2048, 64, 0, "pool boiling 4096x2048 fluid + 4096x64 heater, FP64 populations, "
+                                         "1 hot spot per 64 columns, superheat 0.1 Tc"),
+    "paper": (400, 400, 20, 1, "pool boiling 400x400 fluid + 400x20 heater, FP32-deviation populations, "
+                               "superheat 0.1 Tc"),
+}
+
+
+def algorithmic_bytes(nx, nyf, nys, precision):
+    """Bytes the method must move per step: populations read + written
+    (9 x 8 x 2 FP64 or 9 x 4 x 2 FP32) and T read + written (16) per fluid
+    node, T read + written per heater node."""
+    per_fluid = (144 if precision == 0 else 72) + 16
+    return per_fluid * nx * nyf + 16 * nx * nys
+
+
+def load_traffic(kernel_key):
+    """HBM traffic per step measured with rocprofv3 PMC counters, if the
+    measurement was taken on the current kernel source (hash match)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    src = open(os.path.join(ROOT, "paper_1911_10747_amd", "csrc", "pb_kernels.hip"), "rb").read()
+    if rec.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return rec.get(kernel_key)
+
+
+def cpu_baseline(nx, nyf, nys, steps):
+    """The FP64 oracle, as it stands, on `steps` steps of the same workload
+    (serial C, one core)."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import workloads as W
+    from oracle import eos, orc
+    P = dict(W.BASE_PARAMS)
+    Tc = eos.critical_temperature(P["a"], P["b"], P["R"])
+    Ts = W.T_SAT_OVER_TC * Tc
+    rl, rv, _ = eos.maxwell(Ts, P["a"], P["b"], P["R"], P["omega"], Tc)
+    import numpy as np
+    P.update(nx=nx, nyf=nyf, nys=nys, Tc=Tc, rho_L=rl, rho_V=rv, rho_S=W.RHO_S_OVER_RHO_L * rl)
+    dom = orc.Domain(**P)
+    Tb = W.spot_Tb(nx, Ts + 0.1 * Tc, max(1, nx // 64), 0)
+    gam = np.full(nx, -0.7 * eos.psi(rl, Ts, P["a"], P["b"], P["R"], P["omega"], Tc))
+    dom.set_bc(Ts, Tb, gamma_bot=gam, gamma_top=gam)
+    dom.set_fields(W.layered_rho(nx, nyf, int(round(0.4 * nyf)), rl, rv), W.thermal_init(nx, nys, nyf, Ts, Tb))
+    t0 = time.perf_counter()
+    dom.step(steps)
+    dt = time.perf_counter() - t0
+    return dict(value=nx * nyf * steps / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
+                sample=f"{steps} steps of the full {nx}x{nyf}+{nys} domain, serial FP64 C oracle, one core, "
+                       f"{dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="roofline", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", default="0x0")
+    ap.add_argument("--thermal-tile", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU x-slab sharding is design-only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1911_10747_amd import poolboil as pb
+    from paper_1911_10747_amd import presets
+
+    nx, nyf, nys, prec, desc = WORKLOADS[args.workload]
+    tx, ty = (int(v) for v in args.tile.split("x"))
+    spec = presets.JobSpec(nx=nx, nyf=nyf, nys=nys, superheat=0.1, steps=args.warmup + args.steps, seed=0,
+                           precision=prec, tile=(tx, ty), thermal_tile=args.thermal_tile)
+    torch.cuda.set_device(0)
+    dom = presets.make_domain(spec)
+    dom.flux_window(0, 1 << 62, 10)
+    print(f"bench: {args.workload} {nx}x{nyf}+{nys} prec={prec}: warmup {args.warmup}", file=sys.stderr, flush=True)
+    dom.step(args.warmup)
+    dom.sync()
+    torch.cuda.synchronize()
+    print(f"bench: timing {args.steps} steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    prof = dom.profile_steps(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dom.sync()
+    ms_step = wall / args.steps * 1e3
+    mlups = nx * nyf * args.steps / wall / 1e6
+    alg = algorithmic_bytes(nx, nyf, nys, prec)
+    kern_ms = prof["flow_ms"] + prof["thermal_ms"]
+    achieved = alg / (kern_ms * 1e-3) / 1e9
+    traffic = load_traffic(f"{args.workload}_bytes_per_step")
+    out = {
+        "metric": "MLUPS (fused pool-boiling step, fluid-node updates per second) and fraction of HBM peak",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded pool-boiling start: Maxwell liquid layer, +2% heater hot spots)",
+        "config": {"workload": desc, "nx": nx, "ny_fluid": nyf, "ny_solid": nys,
+                   "storage": "fp32-deviation" if prec else "fp64", "arithmetic": "fp64",
+                   "tile": [tx, ty], "thermal_tile": args.thermal_tile, "parallelism": "single GPU"},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "one step = k_flow + k_thermal (algorithmic bytes of the whole step over the summed "
+                      "mean launch durations)",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_step": alg,
+            "flow_ms": round(prof["flow_ms"], 5),
+            "thermal_ms": round(prof["thermal_ms"], 5),
+        },
+    }
+    dom.close()
+    if not args.no_cpu_baseline:
+        print(f"bench: oracle on {args.cpu_steps} steps", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(nx, nyf, nys, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

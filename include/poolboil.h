@@ -1,0 +1,197 @@
+/*
+ * poolboil.h -- C ABI of the MI355X (gfx950) implementation of the time step
+ * of the hybrid pseudopotential phase-change lattice Boltzmann method for pool
+ * boiling with conjugate heat transfer (Zhao, Liang, Sun, Cai, Li,
+ * arXiv:1911.10747, Section 2; set-up of Section 3.1).
+ *
+ * One time step t -> t+1 of a domain is
+ *   (1) pull streaming of the post-collision populations with halfway
+ *       bounce-back at the walls and periodic x (Eq. 8, Section 3.1);
+ *   (2) the macroscopic update rho = sum f, rho v = sum e f + F/2 (Eq. 10);
+ *   (3) the pseudopotential psi(rho, T(t)) from the Peng-Robinson EOS
+ *       (Eqs. 12-13) and the forces F = F_m + F_ads + F_g (Eqs. 11, 14, 15);
+ *   (4) the energy equation (Eq. 24) advanced by RK4 (Eqs. 25-26) with the
+ *       isotropic stencils (Eqs. 27-28) over the fluid and the solid heater,
+ *       with rho(t), v(t) frozen inside the step;
+ *   (5) the MRT collision with the improved forcing (Eqs. 3-7, 9);
+ *   (6) optionally, the wall heat-flux sample (Eqs. 36, 38, 39).
+ *
+ * Grid and layout.  A domain has nx columns (periodic), ny_fluid fluid rows
+ * and ny_solid heater rows below them.  Thermal rows are numbered
+ * 0 .. ny_solid+ny_fluid-1 from the heater bottom up: rows < ny_solid are
+ * solid, row 0 is held at the Dirichlet value T_b(x, t), and a virtual row
+ * above the last fluid row is held at T_top.  Halfway bounce-back walls sit
+ * between the heater and the first fluid row and above the last fluid row.
+ * Every host array passed in or out is row-major with x fastest:
+ *   rho, ux, uy : [ny_fluid][nx]             (fluid rows, y up)
+ *   T           : [ny_solid + ny_fluid][nx]  (thermal rows, row 0 = heater bottom)
+ *   f           : [9][ny_fluid][nx]          (D2Q9 in the order of Eq. 2)
+ * All values are FP64 at the boundary.  Host arrays are copied; the caller
+ * keeps ownership.  The library never retains a caller pointer after a call
+ * returns, except the device memory given to pb_create_domain.
+ *
+ * Errors.  Every int-returning call returns PB_OK (0) or a negative PB_E*
+ * code; pb_last_error() then gives a message (thread-local).  A handle must
+ * not be used from two threads at once.  Calls that enqueue work are
+ * asynchronous on the domain's stream; pb_sync() waits and reports the sticky
+ * non-finite flag (negative psi radicand, NaN or Inf) as PB_ENONFINITE.
+ */
+#ifndef POOLBOIL_H
+#define POOLBOIL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PB_VERSION 1
+
+enum {
+    PB_OK = 0,
+    PB_EINVAL = -1,      /* bad argument or configuration               */
+    PB_ENOMEM = -2,      /* device allocation failed / buffer too small  */
+    PB_EDEVICE = -3,     /* HIP runtime error                            */
+    PB_ENONFINITE = -4,  /* sticky flag: negative psi radicand or NaN/Inf */
+    PB_ESTATE = -5       /* call not valid in the current state          */
+};
+
+/* Storage precision of the populations.  Arithmetic is FP64 in both modes.
+ * PB_FP32_DEV stores f*_i - w_i rho(x) in FP32 (rho is the node's density,
+ * kept in FP64); T, rho and v stay FP64. */
+enum { PB_FP64 = 0, PB_FP32_DEV = 1 };
+
+/* Configuration flags (pb_config.flags). */
+#define PB_PERIODIC_Y    0x1u  /* periodic in y too: no walls, ny_solid = 0        */
+#define PB_ISOTHERMAL    0x2u  /* skip the energy equation: T stays as set          */
+#define PB_FROZEN_FLOW   0x4u  /* skip the flow: f fixed, v = 0 in Eq. 24           */
+#define PB_SBAR2_PLUS    0x8u  /* + sign of the varpi term in row 2 of Eq. 9        */
+#define PB_VARPI_FM_ONLY 0x10u /* varpi term of Eq. 9 uses F_m of Eq. 11 only
+                                  (default: F_m + F_ads)                          */
+
+/* Flat configuration, copied by pb_create_domain.  Every physical constant is
+ * explicit; the library derives only rho_bar (Eq. 15, mean initial fluid
+ * density) and per-step invariants from it. */
+typedef struct pb_config {
+    int32_t nx, ny_fluid, ny_solid;  /* ny_solid >= 1 unless PB_PERIODIC_Y (then 0);
+                                        heat-flux sampling needs ny_solid >= 3 */
+    int32_t precision;               /* PB_FP64 or PB_FP32_DEV                   */
+    uint32_t flags;                  /* PB_* flags                               */
+    int32_t tile_x, tile_y;          /* flow-kernel tile; 0 = library default    */
+    int32_t thermal_tile;            /* thermal-kernel tile variant; 0 = default */
+    double a, b, R, omega, Tc;       /* Eq. 13 (Tc explicit)                     */
+    double G;                        /* Eq. 11-12 interaction strength (< 0)     */
+    double s_e, s_q, varpi;          /* Eq. 3: s1 = s2 = s_e, s4 = s6 = s_q; Eq. 9 */
+    double tau_L, tau_V, rho_L, rho_V; /* Eq. 5                                  */
+    double g;                        /* Eq. 15: gravity (0, -g)                  */
+    double Cv, Cvchi;                /* fluid C_V and lambda = Cvchi * rho        */
+    double rho_S, C_S, lambda_S;     /* heater density, heat capacity, conductivity */
+} pb_config;
+
+/* Boundary data.  T_bottom_alt (if not NULL) replaces T_bottom for
+ * alt_t0 <= t < alt_t1 (the fluctuating trigger of Section 3.2).  gamma_* are
+ * the per-wall-node adhesion coefficients G_w psi(rho_w) of Eq. 14 (NULL = 0). */
+typedef struct pb_bc {
+    double T_top;
+    const double *T_bottom;      /* [nx], required unless PB_PERIODIC_Y */
+    const double *T_bottom_alt;  /* [nx] or NULL                         */
+    int64_t alt_t0, alt_t1;
+    const double *gamma_bottom;  /* [nx] or NULL                         */
+    const double *gamma_top;     /* [nx] or NULL                         */
+} pb_bc;
+
+/* Heat flux (lattice units).  q_bottom: -lambda_S dT/dy at the heater bottom
+ * with the one-sided second-order difference of Eq. 36 (the quantity of
+ * Eq. 39 before scaling), averaged over x.  q_top: conductive link flux from
+ * the heater top row into the fluid, averaged over x (uses the conductances
+ * of the last completed step).  T_w: mean heater-top temperature (Section
+ * 3.2).  *_mean: averages over the samples of the window (Eq. 38). */
+typedef struct pb_flux {
+    double q_bottom_inst, q_top_inst, T_w_inst;
+    double q_bottom_mean, q_top_mean, T_w_mean;
+    int64_t n_samples;
+} pb_flux;
+
+typedef struct pb_domain pb_domain;
+typedef struct pb_batch pb_batch;
+
+/* Device bytes a domain with this configuration needs (state, boundary data,
+ * flags and flux accumulators; read-back staging is allocated on first read). */
+int pb_domain_bytes(const pb_config *cfg, size_t *bytes);
+
+/* Create a domain.  stream: a hipStream_t (NULL = the null stream).  dev_mem:
+ * NULL to let the library allocate, or caller-owned device memory of at least
+ * pb_domain_bytes() bytes (256-byte aligned) that must outlive the domain.
+ * Fields start at zero; call pb_set_bc and pb_set_fields before stepping. */
+int pb_create_domain(const pb_config *cfg, void *stream, void *dev_mem, size_t dev_bytes, pb_domain **out);
+void pb_destroy_domain(pb_domain *dom);
+
+/* Boundary data (Section 3.1 Dirichlet rows, Section 3.2 trigger, Eq. 14). */
+int pb_set_bc(pb_domain *dom, const pb_bc *bc);
+
+/* Initial state: f = w_i rho (rest equilibrium), T as given (row 0 is then set
+ * to T_b(x, 0)), t = 0, rho_bar = mean of rho, error flag cleared. */
+int pb_set_fields(pb_domain *dom, const double *rho, const double *T);
+
+/* Full state for checkpoint/resume: f(t) after streaming, T(t), the time t and
+ * rho_bar (Eq. 15), all exactly as pb_read_fields/pb_rho_bar returned them. */
+int pb_set_fields_full(pb_domain *dom, const double *f, const double *T, int64_t t, double rho_bar);
+
+/* Enqueue exactly n steps (asynchronous). */
+int pb_step(pb_domain *dom, int64_t n);
+
+/* Wait for the domain's work; PB_ENONFINITE if the sticky flag is set. */
+int pb_sync(pb_domain *dom);
+
+/* Synchronous read of rho(t), v(t) (Eq. 10 with the forces at T(t)), T(t) and,
+ * if f is not NULL, f(t) after streaming.  Any output pointer may be NULL. */
+int pb_read_fields(pb_domain *dom, double *rho, double *ux, double *uy, double *T, double *f);
+
+/* Heat-flux sampling: a sample is taken after every step that ends at a time
+ * t with t_a <= t < t_b and (t - t_a) % every == 0.  Resets the accumulators. */
+int pb_flux_window(pb_domain *dom, int64_t t_a, int64_t t_b, int32_t every);
+int pb_heat_flux(pb_domain *dom, pb_flux *out);   /* synchronous */
+
+/* Diagnostics: enqueue n steps exactly as pb_step does, with HIP events
+ * recorded on the domain's stream around every flow and thermal launch; wait
+ * for them and return the mean launch durations in milliseconds:
+ * avg_ms[0] = flow kernel, avg_ms[1] = thermal kernel, avg_ms[2] = elapsed
+ * time of the whole sequence divided by n.  The steps are real steps. */
+int pb_profile_steps(pb_domain *dom, int64_t n, double *avg_ms);
+
+int64_t pb_time(const pb_domain *dom);            /* current t              */
+double pb_rho_bar(const pb_domain *dom);          /* rho_bar of Eq. 15      */
+
+/* Batched stepping of many domains in shared launches (one flow and one
+ * thermal launch per step for the whole set, tiles of every domain in one
+ * work-list), optionally replayed from a captured HIP graph of
+ * steps_per_graph steps.  All domains must share precision and the stream
+ * given here; they are stepped in lock-step.  Per-node arithmetic does not
+ * depend on the batch, so each domain's result is bit-identical to stepping
+ * it alone.  persistent_blocks > 0 caps the grid (blocks then loop over the
+ * work-list).  The domains must outlive the batch. */
+int pb_batch_create(pb_domain *const *doms, int32_t n, int32_t steps_per_graph, int32_t persistent_blocks,
+                    void *stream, pb_batch **out);
+int pb_batch_step(pb_batch *batch, int64_t n);
+void pb_batch_destroy(pb_batch *batch);
+
+/* Host helpers for configuration (no device work): the critical temperature
+ * implied by a = 0.45724 R^2 Tc^2/Pc and b = 0.0778 R Tc/Pc (Section 2.1), and
+ * the Maxwell coexistence densities of Eq. 13 at temperature T (Section 3.1). */
+int pb_eos_critical_temperature(double a, double b, double R, double *Tc);
+int pb_eos_coexistence(double a, double b, double R, double omega, double Tc, double T, double *rho_L,
+                       double *rho_V);
+
+/* psi of Eq. 12 (c = 1, c_s^2 = 1/3) with P_EOS of Eq. 13 at (rho, T); used
+ * to express wall adhesion gamma = G_w psi(rho_w) of Eq. 14. */
+int pb_eos_psi(double a, double b, double R, double omega, double Tc, double G, double rho, double T, double *psi);
+
+const char *pb_last_error(void);
+int pb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POOLBOIL_H */

@@ -1,0 +1,871 @@
+// Host side of the C ABI declared in include/poolboil.h: domain lifecycle,
+// boundary data, state upload/read-back, stepping, heat flux, batched and
+// graph-replayed stepping, and host EOS helpers for building configurations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/poolboil.h"
+#include "pb_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define PB_HIP(call)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) return fail(PB_EDEVICE, "%s: %s", #call, hipGetErrorString(e_));     \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+const double kWh[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+const int kEXh[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+const int kEYh[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+const int kOPPh[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+int flow_variant_of(const pb_config &c) {
+    if (c.tile_x == 0 && c.tile_y == 0) return 0;
+    for (int v = 0; v < pb_flow_variants(); ++v) {
+        int bx, by;
+        pb_flow_tile_shape(v, &bx, &by);
+        if (bx == c.tile_x && by == c.tile_y) return v;
+    }
+    return -1;
+}
+
+int ntiles_for(int nx, int ny, int bx, int by) { return ((nx + bx - 1) / bx) * ((ny + by - 1) / by); }
+
+int max_tiles(int nx, int ny, bool flow) {
+    int m = 0, nv = flow ? pb_flow_variants() : pb_thermal_variants();
+    for (int v = 0; v < nv; ++v) {
+        int bx, by;
+        if (flow) pb_flow_tile_shape(v, &bx, &by); else pb_thermal_tile_shape(v, &bx, &by);
+        m = std::max(m, ntiles_for(nx, ny, bx, by));
+    }
+    return m;
+}
+
+// Arena layout of one domain (offsets in bytes from the base).
+struct Layout {
+    size_t desc, dptr, f[2], rho[2], vx, vy, T[2], Tb, Tba, gb, gt, err, flux, tflow, tth, total;
+};
+
+Layout layout_of(const pb_config &c) {
+    Layout L{};
+    const size_t pitch = align_up((size_t)c.nx, 64);
+    const size_t nf = (size_t)c.ny_fluid * pitch, nt = (size_t)(c.ny_fluid + c.ny_solid) * pitch;
+    const size_t es = c.precision == PB_FP32_DEV ? 4 : 8;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, kAlign); return r; };
+    L.desc = take(sizeof(PbDesc));
+    L.dptr = take(sizeof(void *));
+    L.f[0] = take(9 * nf * es);
+    L.f[1] = take(9 * nf * es);
+    L.rho[0] = take(nf * 8);
+    L.rho[1] = take(nf * 8);
+    L.vx = take(nf * 8);
+    L.vy = take(nf * 8);
+    L.T[0] = take(nt * 8);
+    L.T[1] = take(nt * 8);
+    L.Tb = take((size_t)c.nx * 8);
+    L.Tba = take((size_t)c.nx * 8);
+    L.gb = take((size_t)c.nx * 8);
+    L.gt = take((size_t)c.nx * 8);
+    L.err = take(sizeof(int32_t));
+    L.flux = take(8 * sizeof(double));
+    L.tflow = take((size_t)max_tiles(c.nx, c.ny_fluid, true) * sizeof(PbTile));
+    L.tth = take((size_t)max_tiles(c.nx, c.ny_fluid + c.ny_solid, false) * sizeof(PbTile));
+    L.total = o;
+    return L;
+}
+
+int validate(const pb_config *c) {
+    if (!c) return fail(PB_EINVAL, "config is NULL");
+    if (c->nx < 1 || c->ny_fluid < 1) return fail(PB_EINVAL, "nx and ny_fluid must be >= 1");
+    if (c->nx > (1 << 20) || c->ny_fluid > (1 << 20) || c->ny_solid > (1 << 20))
+        return fail(PB_EINVAL, "domain dimension above 2^20");
+    if (c->precision != PB_FP64 && c->precision != PB_FP32_DEV) return fail(PB_EINVAL, "unknown precision %d", c->precision);
+    if (c->flags & ~0x1Fu) return fail(PB_EINVAL, "unknown flag bits 0x%x", c->flags);
+    const bool pery = (c->flags & PB_PERIODIC_Y) != 0;
+    if (pery && c->ny_solid != 0) return fail(PB_EINVAL, "PB_PERIODIC_Y needs ny_solid == 0");
+    if (!pery && c->ny_solid < 1) return fail(PB_EINVAL, "ny_solid must be >= 1 (row 0 is the Dirichlet heater bottom)");
+    if (!(c->G < 0.0)) return fail(PB_EINVAL, "G must be negative (Eq. 12)");
+    if (!(c->Tc > 0.0) || !(c->b > 0.0) || !(c->R > 0.0)) return fail(PB_EINVAL, "Tc, b and R must be positive");
+    if (!(c->rho_L > c->rho_V) || !(c->rho_V > 0.0)) return fail(PB_EINVAL, "need rho_L > rho_V > 0");
+    if (!(c->Cv > 0.0) || !(c->Cvchi > 0.0) || !(c->lambda_S > 0.0) || !(c->rho_S > 0.0) || !(c->C_S > 0.0))
+        return fail(PB_EINVAL, "thermal properties must be positive");
+    if (!(c->s_e > 0.0 && c->s_e < 2.0) || !(c->s_q > 0.0 && c->s_q < 2.0))
+        return fail(PB_EINVAL, "relaxation rates must lie in (0, 2)");
+    if (!(c->tau_L > 0.5) || !(c->tau_V > 0.5)) return fail(PB_EINVAL, "relaxation times must exceed 1/2");
+    if (flow_variant_of(*c) < 0) return fail(PB_EINVAL, "no flow tile %dx%d", c->tile_x, c->tile_y);
+    if (c->thermal_tile < 0 || c->thermal_tile >= pb_thermal_variants())
+        return fail(PB_EINVAL, "no thermal tile variant %d", c->thermal_tile);
+    return PB_OK;
+}
+
+// Order tiles so that the hardware's round-robin placement of consecutive
+// workgroups over the 8 XCDs gives each XCD a contiguous band of tiles (halo
+// re-reads then hit that XCD's L2).
+void xcd_order(std::vector<PbTile> &tiles) {
+    const int n = (int)tiles.size(), X = 8;
+    if (n < 2 * X) return;
+    std::vector<PbTile> out(n);
+    const int q = n / X, r = n % X;
+    for (int b = 0; b < n; ++b) {
+        const int j = b % X, s = b / X;
+        const int off = j * q + std::min(j, r);
+        out[b] = tiles[off + s];
+    }
+    tiles.swap(out);
+}
+
+void make_tiles(std::vector<PbTile> &out, int dom, int nx, int ny, int bx, int by) {
+    for (int y0 = 0; y0 < ny; y0 += by)
+        for (int x0 = 0; x0 < nx; x0 += bx) out.push_back(PbTile{dom, x0, y0, 0});
+}
+
+}  // namespace
+
+struct pb_domain {
+    pb_config cfg{};
+    hipStream_t stream = nullptr;
+    char *base = nullptr;
+    bool owns = false;
+    Layout L{};
+    PbDesc hd{};                 // host mirror of the device descriptor
+    PbDesc *ddesc = nullptr;     // device descriptor
+    PbDesc **dptr = nullptr;     // device array holding the one pointer ddesc
+    int pitch = 0, nr = 0;
+    int64_t t = 0;
+    int par = 0;
+    bool fields_set = false;
+    int fvar = 0, tvar = 0;
+    int nt_flow = 0, nt_th = 0;
+    PbTile *dtiles_flow = nullptr, *dtiles_th = nullptr;
+    std::vector<double> Tb, Tba, gb, gt;
+    double *rd = nullptr;        // read-back staging (lazy)
+};
+
+struct pb_batch {
+    std::vector<pb_domain *> doms;
+    hipStream_t stream = nullptr;
+    int prec = 0, fvar = 0, tvar = 0;
+    int nt_flow = 0, nt_th = 0, grid_flow = 0, grid_th = 0;
+    int spg = 0;
+    PbDesc **dptrs = nullptr;
+    PbTile *dtiles_flow = nullptr, *dtiles_th = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    bool any_flux = true;
+    bool owns_stream = false;
+    hipEvent_t ev_batch = nullptr, ev_dom = nullptr;
+    std::vector<hipStream_t> dom_streams;   // distinct member streams
+};
+
+namespace {
+
+int upload_desc(pb_domain *d) {
+    d->hd.t0 = d->t;
+    d->hd.par0 = d->par;
+    PB_HIP(hipMemcpyAsync(d->ddesc, &d->hd, sizeof(PbDesc), hipMemcpyHostToDevice, d->stream));
+    PB_HIP(hipStreamSynchronize(d->stream));
+    return PB_OK;
+}
+
+int upload_tiles(pb_domain *d) {
+    int bx, by;
+    std::vector<PbTile> tf, tt;
+    pb_flow_tile_shape(d->fvar, &bx, &by);
+    make_tiles(tf, 0, d->cfg.nx, d->cfg.ny_fluid, bx, by);
+    pb_thermal_tile_shape(d->tvar, &bx, &by);
+    make_tiles(tt, 0, d->cfg.nx, d->nr, bx, by);
+    xcd_order(tf);
+    xcd_order(tt);
+    d->nt_flow = (int)tf.size();
+    d->nt_th = (int)tt.size();
+    PB_HIP(hipMemcpyAsync(d->dtiles_flow, tf.data(), tf.size() * sizeof(PbTile), hipMemcpyHostToDevice, d->stream));
+    PB_HIP(hipMemcpyAsync(d->dtiles_th, tt.data(), tt.size() * sizeof(PbTile), hipMemcpyHostToDevice, d->stream));
+    PB_HIP(hipStreamSynchronize(d->stream));
+    return PB_OK;
+}
+
+double bc_bottom(const pb_domain *d, int x, int64_t t) {
+    if (!d->Tba.empty() && t >= d->hd.alt_t0 && t < d->hd.alt_t1) return d->Tba[x];
+    return d->Tb.empty() ? d->hd.T_top : d->Tb[x];
+}
+
+int copy_rows_h2d(pb_domain *d, void *dst, const double *src, int rows) {
+    PB_HIP(hipMemcpy2DAsync(dst, (size_t)d->pitch * 8, src, (size_t)d->cfg.nx * 8, (size_t)d->cfg.nx * 8, rows,
+                            hipMemcpyHostToDevice, d->stream));
+    return PB_OK;
+}
+
+int copy_rows_d2h(pb_domain *d, double *dst, const void *src, int rows) {
+    PB_HIP(hipMemcpy2DAsync(dst, (size_t)d->cfg.nx * 8, src, (size_t)d->pitch * 8, (size_t)d->cfg.nx * 8, rows,
+                            hipMemcpyDeviceToHost, d->stream));
+    return PB_OK;
+}
+
+int check_dom(const pb_domain *d) {
+    if (!d) return fail(PB_EINVAL, "domain is NULL");
+    return PB_OK;
+}
+
+int enqueue_steps(pb_domain *d, int64_t n) {
+    const bool frozen = d->cfg.flags & PB_FROZEN_FLOW, iso = d->cfg.flags & PB_ISOTHERMAL;
+    const bool sampling = !(d->cfg.flags & PB_PERIODIC_Y) && d->cfg.ny_solid >= 3 && d->hd.fl_tb > d->hd.fl_ta;
+    const PbDesc *const *dp = (const PbDesc *const *)d->dptr;
+    // the descriptor's kernel step index is an int; long runs are split
+    const int64_t chunk = 1 << 30;
+    while (n > 0) {
+        const int m = (int)std::min<int64_t>(n, chunk);
+        for (int k = 0; k < m; ++k) {
+            if (!frozen) PB_HIP(pb_launch_flow(d->cfg.precision, PB_MODE_STEP, d->fvar, dp, d->dtiles_flow, d->nt_flow,
+                                               d->nt_flow, k, d->stream));
+            if (!iso) PB_HIP(pb_launch_thermal(d->tvar, dp, d->dtiles_th, d->nt_th, d->nt_th, k, d->stream));
+            const int64_t tk = d->t + k + 1;
+            if (sampling && tk >= d->hd.fl_ta && tk < d->hd.fl_tb && (tk - d->hd.fl_ta) % d->hd.fl_every == 0)
+                PB_HIP(pb_launch_flux(dp, 1, k, d->stream));
+        }
+        PB_HIP(pb_launch_advance(d->dptr, 1, m, d->stream));
+        d->t += m;
+        d->par ^= (m & 1);
+        n -= m;
+    }
+    d->hd.t0 = d->t;
+    d->hd.par0 = d->par;
+    return PB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pb_version(void) { return PB_VERSION; }
+const char *pb_last_error(void) { return g_err.c_str(); }
+
+int pb_domain_bytes(const pb_config *cfg, size_t *bytes) {
+    int rc = validate(cfg);
+    if (rc) return rc;
+    if (!bytes) return fail(PB_EINVAL, "bytes is NULL");
+    *bytes = layout_of(*cfg).total;
+    return PB_OK;
+}
+
+int pb_create_domain(const pb_config *cfg, void *stream, void *dev_mem, size_t dev_bytes, pb_domain **out) {
+    int rc = validate(cfg);
+    if (rc) return rc;
+    if (!out) return fail(PB_EINVAL, "out is NULL");
+    *out = nullptr;
+    pb_domain *d = new (std::nothrow) pb_domain();
+    if (!d) return fail(PB_ENOMEM, "host allocation failed");
+    d->cfg = *cfg;
+    d->stream = (hipStream_t)stream;
+    d->L = layout_of(*cfg);
+    d->pitch = (int)align_up((size_t)cfg->nx, 64);
+    d->nr = cfg->ny_fluid + cfg->ny_solid;
+    d->fvar = flow_variant_of(*cfg);
+    d->tvar = cfg->thermal_tile;
+    if (dev_mem) {
+        if (dev_bytes < d->L.total) {
+            delete d;
+            return fail(PB_ENOMEM, "device buffer of %zu bytes, %zu needed", dev_bytes, d->L.total);
+        }
+        if ((uintptr_t)dev_mem % kAlign) {
+            delete d;
+            return fail(PB_EINVAL, "device buffer must be %zu-byte aligned", kAlign);
+        }
+        d->base = (char *)dev_mem;
+    } else {
+        if (hipMalloc((void **)&d->base, d->L.total) != hipSuccess) {
+            delete d;
+            return fail(PB_ENOMEM, "hipMalloc of %zu bytes failed", d->L.total);
+        }
+        d->owns = true;
+    }
+    const Layout &L = d->L;
+    PbDesc &h = d->hd;
+    memset(&h, 0, sizeof(h));
+    h.nx = cfg->nx;
+    h.nyf = cfg->ny_fluid;
+    h.nys = cfg->ny_solid;
+    h.nr = d->nr;
+    h.pitch = d->pitch;
+    h.flags = cfg->flags;
+    for (int b = 0; b < 2; ++b) {
+        h.f[b] = d->base + L.f[b];
+        h.rho[b] = (double *)(d->base + L.rho[b]);
+        h.T[b] = (double *)(d->base + L.T[b]);
+    }
+    h.vx = (double *)(d->base + L.vx);
+    h.vy = (double *)(d->base + L.vy);
+    h.Tb = (const double *)(d->base + L.Tb);
+    h.Tb_alt = (const double *)(d->base + L.Tba);
+    h.gbot = (const double *)(d->base + L.gb);
+    h.gtop = (const double *)(d->base + L.gt);
+    h.err = (int32_t *)(d->base + L.err);
+    h.flux = (double *)(d->base + L.flux);
+    h.fl_every = 1;
+    h.a = cfg->a;
+    h.b = cfg->b;
+    h.R = cfg->R;
+    h.kappa = 0.37464 + 1.54226 * cfg->omega - 0.26992 * cfg->omega * cfg->omega;   // Eq. 13
+    h.Tc = cfg->Tc;
+    h.sqrtTc = std::sqrt(cfg->Tc);
+    h.inv_sqrtTc = 1.0 / h.sqrtTc;
+    h.G = cfg->G;
+    h.s_e = cfg->s_e;
+    h.s_q = cfg->s_q;
+    h.varpi = cfg->varpi;
+    h.tau_V = cfg->tau_V;
+    h.rho_V = cfg->rho_V;
+    h.ktau = (cfg->tau_L - cfg->tau_V) / (cfg->rho_L - cfg->rho_V);                    // Eq. 5
+    h.g = cfg->g;
+    h.Cv = cfg->Cv;
+    h.Cvchi = cfg->Cvchi;
+    h.rho_S = cfg->rho_S;
+    h.C_S = cfg->C_S;
+    h.lambda_S = cfg->lambda_S;
+    d->ddesc = (PbDesc *)(d->base + L.desc);
+    d->dptr = (PbDesc **)(d->base + L.dptr);
+    d->dtiles_flow = (PbTile *)(d->base + L.tflow);
+    d->dtiles_th = (PbTile *)(d->base + L.tth);
+    auto cleanup = [&](int code) {
+        if (d->owns) (void)hipFree(d->base);
+        delete d;
+        return code;
+    };
+    // zero the whole state once (fields, boundary arrays, flags, accumulators)
+    if (hipMemsetAsync(d->base, 0, L.total, d->stream) != hipSuccess) return cleanup(fail(PB_EDEVICE, "memset failed"));
+    if (hipMemcpyAsync(d->dptr, &d->ddesc, sizeof(void *), hipMemcpyHostToDevice, d->stream) != hipSuccess)
+        return cleanup(fail(PB_EDEVICE, "descriptor pointer upload failed"));
+    if ((rc = upload_tiles(d))) return cleanup(rc);
+    if ((rc = upload_desc(d))) return cleanup(rc);
+    *out = d;
+    return PB_OK;
+}
+
+void pb_destroy_domain(pb_domain *d) {
+    if (!d) return;
+    (void)hipStreamSynchronize(d->stream);
+    if (d->rd) (void)hipFree(d->rd);
+    if (d->owns) (void)hipFree(d->base);
+    delete d;
+}
+
+int pb_set_bc(pb_domain *d, const pb_bc *bc) {
+    int rc = check_dom(d);
+    if (rc) return rc;
+    if (!bc) return fail(PB_EINVAL, "bc is NULL");
+    const bool pery = d->cfg.flags & PB_PERIODIC_Y;
+    if (!pery && !bc->T_bottom) return fail(PB_EINVAL, "T_bottom is required with walls");
+    const int nx = d->cfg.nx;
+    d->Tb.assign(nx, bc->T_top);
+    if (bc->T_bottom) d->Tb.assign(bc->T_bottom, bc->T_bottom + nx);
+    d->Tba.clear();
+    if (bc->T_bottom_alt) d->Tba.assign(bc->T_bottom_alt, bc->T_bottom_alt + nx);
+    d->gb.assign(nx, 0.0);
+    d->gt.assign(nx, 0.0);
+    if (bc->gamma_bottom) d->gb.assign(bc->gamma_bottom, bc->gamma_bottom + nx);
+    if (bc->gamma_top) d->gt.assign(bc->gamma_top, bc->gamma_top + nx);
+    const std::vector<double> &alt = d->Tba.empty() ? d->Tb : d->Tba;
+    PB_HIP(hipStreamSynchronize(d->stream));
+    PB_HIP(hipMemcpyAsync((void *)d->hd.Tb, d->Tb.data(), nx * 8, hipMemcpyHostToDevice, d->stream));
+    PB_HIP(hipMemcpyAsync((void *)d->hd.Tb_alt, alt.data(), nx * 8, hipMemcpyHostToDevice, d->stream));
+    PB_HIP(hipMemcpyAsync((void *)d->hd.gbot, d->gb.data(), nx * 8, hipMemcpyHostToDevice, d->stream));
+    PB_HIP(hipMemcpyAsync((void *)d->hd.gtop, d->gt.data(), nx * 8, hipMemcpyHostToDevice, d->stream));
+    d->hd.T_top = bc->T_top;
+    d->hd.alt_t0 = bc->T_bottom_alt ? bc->alt_t0 : 0;
+    d->hd.alt_t1 = bc->T_bottom_alt ? bc->alt_t1 : 0;
+    return upload_desc(d);
+}
+
+int pb_set_fields(pb_domain *d, const double *rho, const double *T) {
+    int rc = check_dom(d);
+    if (rc) return rc;
+    if (!rho || !T) return fail(PB_EINVAL, "rho and T are required");
+    const int nx = d->cfg.nx, nyf = d->cfg.ny_fluid;
+    double sum = 0.0;
+    for (size_t i = 0; i < (size_t)nx * nyf; ++i) {
+        if (!(rho[i] > 0.0) || !std::isfinite(rho[i])) return fail(PB_EINVAL, "rho must be positive and finite");
+        sum += rho[i];
+    }
+    std::vector<double> Th(T, T + (size_t)nx * d->nr);
+    if (!(d->cfg.flags & PB_PERIODIC_Y))
+        for (int x = 0; x < nx; ++x) Th[x] = bc_bottom(d, x, 0);
+    PB_HIP(hipStreamSynchronize(d->stream));
+    d->t = 0;
+    d->par = 0;
+    d->hd.rho_bar = sum / ((double)nx * nyf);
+    if ((rc = copy_rows_h2d(d, d->hd.rho[0], rho, nyf))) return rc;
+    for (int b = 0; b < 2; ++b)
+        if ((rc = copy_rows_h2d(d, d->hd.T[b], Th.data(), d->nr))) return rc;
+    PB_HIP(hipMemsetAsync(d->hd.err, 0, sizeof(int32_t), d->stream));
+    if ((rc = upload_desc(d))) return rc;
+    PB_HIP(pb_launch_init(d->cfg.precision, d->ddesc, 0, d->stream));
+    PB_HIP(hipStreamSynchronize(d->stream));
+    d->fields_set = true;
+    return PB_OK;
+}
+
+int pb_set_fields_full(pb_domain *d, const double *f, const double *T, int64_t t, double rho_bar) {
+    int rc = check_dom(d);
+    if (rc) return rc;
+    if (!f || !T) return fail(PB_EINVAL, "f and T are required");
+    if (d->cfg.flags & PB_FROZEN_FLOW) return fail(PB_EINVAL, "full state upload is not supported with PB_FROZEN_FLOW");
+    if (t < 0) return fail(PB_EINVAL, "t must be >= 0");
+    const int nx = d->cfg.nx, nyf = d->cfg.ny_fluid;
+    const bool pery = d->cfg.flags & PB_PERIODIC_Y;
+    const size_t np = (size_t)nx * nyf;
+    // Undo the streaming: slot (i, y) is pulled by y + e_i as f_i, or, when
+    // y + e_i is a wall, by y itself as f_opp(i) (bounce-back).
+    std::vector<double> fs(9 * np), rref(np, 0.0);
+    for (int y = 0; y < nyf; ++y)
+        for (int x = 0; x < nx; ++x)
+            for (int i = 0; i < 9; ++i) {
+                const int xd = (x + kEXh[i] + nx) % nx;
+                int yd = y + kEYh[i];
+                double v;
+                if (pery) yd = (yd + nyf) % nyf;
+                if (yd >= 0 && yd < nyf) v = f[(size_t)i * np + (size_t)yd * nx + xd];
+                else v = f[(size_t)kOPPh[i] * np + (size_t)y * nx + x];
+                fs[(size_t)i * np + (size_t)y * nx + x] = v;
+            }
+    for (size_t n = 0; n < np; ++n) {
+        double s = 0.0;
+        for (int i = 0; i < 9; ++i) s += fs[(size_t)i * np + n];
+        rref[n] = s;
+    }
+    PB_HIP(hipStreamSynchronize(d->stream));
+    const int par = 0;
+    if (d->cfg.precision == PB_FP64) {
+        for (int i = 0; i < 9; ++i)
+            if ((rc = copy_rows_h2d(d, (double *)d->hd.f[par] + (size_t)i * nyf * d->pitch, fs.data() + (size_t)i * np,
+                                    nyf)))
+                return rc;
+    } else {
+        std::vector<float> dev(9 * np);
+        for (int i = 0; i < 9; ++i)
+            for (size_t n = 0; n < np; ++n) dev[(size_t)i * np + n] = (float)(fs[(size_t)i * np + n] - kWh[i] * rref[n]);
+        for (int i = 0; i < 9; ++i)
+            PB_HIP(hipMemcpy2DAsync((float *)d->hd.f[par] + (size_t)i * nyf * d->pitch, (size_t)d->pitch * 4,
+                                    dev.data() + (size_t)i * np, (size_t)nx * 4, (size_t)nx * 4, nyf,
+                                    hipMemcpyHostToDevice, d->stream));
+        PB_HIP(hipStreamSynchronize(d->stream));
+    }
+    if ((rc = copy_rows_h2d(d, d->hd.rho[par], rref.data(), nyf))) return rc;
+    for (int b = 0; b < 2; ++b)
+        if ((rc = copy_rows_h2d(d, d->hd.T[b], T, d->nr))) return rc;
+    PB_HIP(hipMemsetAsync(d->hd.err, 0, sizeof(int32_t), d->stream));
+    d->t = t;
+    d->par = par;
+    d->hd.rho_bar = rho_bar;
+    if ((rc = upload_desc(d))) return rc;
+    d->fields_set = true;
+    return PB_OK;
+}
+
+int pb_step(pb_domain *d, int64_t n) {
+    int rc = check_dom(d);
+    if (rc) return rc;
+    if (!d->fields_set) return fail(PB_ESTATE, "pb_set_fields was not called");
+    if (n < 0) return fail(PB_EINVAL, "n must be >= 0");
+    if (n == 0) return PB_OK;
+    return enqueue_steps(d, n);
+}
+
+int pb_sync(pb_domain *d) {
+    int rc = check_dom(d);
+    if (rc) return rc;
+    PB_HIP(hipStreamSynchronize(d->stream));
+    int32_t e = 0;
+    PB_HIP(hipMemcpy(&e, d->hd.err, sizeof(e), hipMemcpyDeviceToHost));
+    if (e) return fail(PB_ENONFINITE, "non-finite value or negative psi radicand (t <= %lld)", (long long)d->t);
+    return PB_OK;
+}
+
+int pb_read_fields(pb_domain *d, double *rho, double *ux, double *uy, double *T, double *f) {
+    int rc = check_dom(d);
+    if (rc) return rc;
+    if (!d->fields_set) return fail(PB_ESTATE, "pb_set_fields was not called");
+    const int nyf = d->cfg.ny_fluid;
+    const size_t nf = (size_t)nyf * d->pitch;
+    PB_HIP(hipStreamSynchronize(d->stream));
+    if (!d->rd) {
+        if (hipMalloc((void **)&d->rd, 12 * nf * sizeof(double)) != hipSuccess)
+            return fail(PB_ENOMEM, "read staging allocation failed");
+        d->hd.rd_f = d->rd;
+        d->hd.rd_rho = d->rd + 9 * nf;
+        d->hd.rd_vx = d->rd + 10 * nf;
+        d->hd.rd_vy = d->rd + 11 * nf;
+        if ((rc = upload_desc(d))) return rc;
+    }
+    if (rho || ux || uy || f) {
+        PB_HIP(pb_launch_flow(d->cfg.precision, PB_MODE_READ, d->fvar, (const PbDesc *const *)d->dptr, d->dtiles_flow,
+                              d->nt_flow, d->nt_flow, 0, d->stream));
+    }
+    if (rho && (rc = copy_rows_d2h(d, rho, d->hd.rd_rho, nyf))) return rc;
+    if (ux && (rc = copy_rows_d2h(d, ux, d->hd.rd_vx, nyf))) return rc;
+    if (uy && (rc = copy_rows_d2h(d, uy, d->hd.rd_vy, nyf))) return rc;
+    if (T && (rc = copy_rows_d2h(d, T, d->hd.T[d->par], d->nr))) return rc;
+    if (f)
+        for (int i = 0; i < 9; ++i)
+            if ((rc = copy_rows_d2h(d, f + (size_t)i * nyf * d->cfg.nx, d->hd.rd_f + (size_t)i * nf, nyf))) return rc;
+    PB_HIP(hipStreamSynchronize(d->stream));
+    return PB_OK;
+}
+
+int pb_flux_window(pb_domain *d, int64_t t_a, int64_t t_b, int32_t every) {
+    int rc = check_dom(d);
+    if (rc) return rc;
+    if (every < 1) return fail(PB_EINVAL, "every must be >= 1");
+    if (!(d->cfg.flags & PB_PERIODIC_Y) && d->cfg.ny_solid < 3 && t_b > t_a)
+        return fail(PB_EINVAL, "heat-flux sampling needs ny_solid >= 3 (Eq. 36 uses rows 0-2)");
+    PB_HIP(hipStreamSynchronize(d->stream));
+    const double zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    PB_HIP(hipMemcpyAsync(d->hd.flux, zero, sizeof(zero), hipMemcpyHostToDevice, d->stream));
+    d->hd.fl_ta = t_a;
+    d->hd.fl_tb = t_b;
+    d->hd.fl_every = every;
+    return upload_desc(d);
+}
+
+int pb_heat_flux(pb_domain *d, pb_flux *out) {
+    int rc = check_dom(d);
+    if (rc) return rc;
+    if (!out) return fail(PB_EINVAL, "out is NULL");
+    double v[8];
+    PB_HIP(hipStreamSynchronize(d->stream));
+    PB_HIP(hipMemcpy(v, d->hd.flux, sizeof(v), hipMemcpyDeviceToHost));
+    const double n = v[6];
+    out->q_bottom_inst = v[0];
+    out->q_top_inst = v[1];
+    out->T_w_inst = v[2];
+    out->q_bottom_mean = n > 0 ? v[3] / n : 0.0;
+    out->q_top_mean = n > 0 ? v[4] / n : 0.0;
+    out->T_w_mean = n > 0 ? v[5] / n : 0.0;
+    out->n_samples = (int64_t)n;
+    return PB_OK;
+}
+
+int pb_profile_steps(pb_domain *d, int64_t n, double *avg_ms) {
+    int rc = check_dom(d);
+    if (rc) return rc;
+    if (!d->fields_set) return fail(PB_ESTATE, "pb_set_fields was not called");
+    if (!avg_ms) return fail(PB_EINVAL, "avg_ms is NULL");
+    if (n < 1 || n > (1 << 20)) return fail(PB_EINVAL, "n must be in [1, 2^20]");
+    const bool frozen = d->cfg.flags & PB_FROZEN_FLOW, iso = d->cfg.flags & PB_ISOTHERMAL;
+    const bool sampling = !(d->cfg.flags & PB_PERIODIC_Y) && d->cfg.ny_solid >= 3 && d->hd.fl_tb > d->hd.fl_ta;
+    const PbDesc *const *dp = (const PbDesc *const *)d->dptr;
+    const int m = (int)n;
+    // events e[2k] before the flow launch of step k, e[2k+1] between flow and
+    // thermal, e[2k+2] after the thermal launch
+    std::vector<hipEvent_t> ev(2 * (size_t)m + 1, nullptr);
+    auto release = [&]() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) { release(); return fail(PB_EDEVICE, "event creation failed"); }
+    hipError_t err = hipSuccess;
+    for (int k = 0; k < m && err == hipSuccess; ++k) {
+        err = hipEventRecord(ev[2 * k], d->stream);
+        if (err == hipSuccess && !frozen)
+            err = pb_launch_flow(d->cfg.precision, PB_MODE_STEP, d->fvar, dp, d->dtiles_flow, d->nt_flow, d->nt_flow, k,
+                                 d->stream);
+        if (err == hipSuccess) err = hipEventRecord(ev[2 * k + 1], d->stream);
+        if (err == hipSuccess && !iso) err = pb_launch_thermal(d->tvar, dp, d->dtiles_th, d->nt_th, d->nt_th, k, d->stream);
+        const int64_t tk = d->t + k + 1;
+        if (err == hipSuccess && sampling && tk >= d->hd.fl_ta && tk < d->hd.fl_tb &&
+            (tk - d->hd.fl_ta) % d->hd.fl_every == 0)
+            err = pb_launch_flux(dp, 1, k, d->stream);
+    }
+    if (err == hipSuccess) err = hipEventRecord(ev[2 * m], d->stream);
+    if (err == hipSuccess) err = pb_launch_advance(d->dptr, 1, m, d->stream);
+    if (err == hipSuccess) err = hipStreamSynchronize(d->stream);
+    if (err != hipSuccess) { release(); return fail(PB_EDEVICE, "profiled steps failed: %s", hipGetErrorString(err)); }
+    d->t += m;
+    d->par ^= (m & 1);
+    d->hd.t0 = d->t;
+    d->hd.par0 = d->par;
+    double sf = 0.0, st = 0.0;
+    float ms;
+    for (int k = 0; k < m; ++k) {
+        (void)hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]);
+        sf += ms;
+        (void)hipEventElapsedTime(&ms, ev[2 * k + 1], ev[2 * k + 2]);
+        st += ms;
+    }
+    (void)hipEventElapsedTime(&ms, ev[0], ev[2 * m]);
+    avg_ms[0] = sf / m;
+    avg_ms[1] = st / m;
+    avg_ms[2] = (double)ms / m;
+    release();
+    return PB_OK;
+}
+
+int64_t pb_time(const pb_domain *d) { return d ? d->t : -1; }
+double pb_rho_bar(const pb_domain *d) { return d ? d->hd.rho_bar : 0.0; }
+
+// ------------------------------------------------------------------ batches
+int pb_batch_create(pb_domain *const *doms, int32_t n, int32_t steps_per_graph, int32_t persistent_blocks, void *stream,
+                    pb_batch **out) {
+    if (!out) return fail(PB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!doms || n < 1) return fail(PB_EINVAL, "need at least one domain");
+    if (steps_per_graph < 0 || (steps_per_graph & 1)) return fail(PB_EINVAL, "steps_per_graph must be even and >= 0");
+    if (persistent_blocks < 0) return fail(PB_EINVAL, "persistent_blocks must be >= 0");
+    const int prec = doms[0]->cfg.precision;
+    for (int j = 0; j < n; ++j) {
+        if (!doms[j]) return fail(PB_EINVAL, "domain %d is NULL", j);
+        if (!doms[j]->fields_set) return fail(PB_ESTATE, "domain %d has no fields", j);
+        if (doms[j]->cfg.precision != prec) return fail(PB_EINVAL, "mixed precisions in one batch");
+        if (doms[j]->cfg.flags & (PB_FROZEN_FLOW | PB_ISOTHERMAL))
+            return fail(PB_EINVAL, "batches step the full method (no frozen/isothermal domains)");
+        for (int i = 0; i < j; ++i)
+            if (doms[i] == doms[j]) return fail(PB_EINVAL, "domain listed twice");
+    }
+    pb_batch *b = new (std::nothrow) pb_batch();
+    if (!b) return fail(PB_ENOMEM, "host allocation failed");
+    b->doms.assign(doms, doms + n);
+    b->stream = (hipStream_t)stream;
+    for (int j = 0; j < n; ++j)
+        if (std::find(b->dom_streams.begin(), b->dom_streams.end(), doms[j]->stream) == b->dom_streams.end())
+            b->dom_streams.push_back(doms[j]->stream);
+    b->prec = prec;
+    b->fvar = doms[0]->fvar;
+    b->tvar = doms[0]->tvar;
+    b->spg = steps_per_graph;
+    std::vector<PbTile> tf, tt;
+    std::vector<PbDesc *> ptrs(n);
+    int fbx, fby, tbx, tby;
+    pb_flow_tile_shape(b->fvar, &fbx, &fby);
+    pb_thermal_tile_shape(b->tvar, &tbx, &tby);
+    for (int j = 0; j < n; ++j) {
+        make_tiles(tf, j, doms[j]->cfg.nx, doms[j]->cfg.ny_fluid, fbx, fby);
+        make_tiles(tt, j, doms[j]->cfg.nx, doms[j]->nr, tbx, tby);
+        ptrs[j] = doms[j]->ddesc;
+    }
+    b->nt_flow = (int)tf.size();
+    b->nt_th = (int)tt.size();
+    b->grid_flow = persistent_blocks > 0 ? std::min(b->nt_flow, (int)persistent_blocks) : b->nt_flow;
+    b->grid_th = persistent_blocks > 0 ? std::min(b->nt_th, (int)persistent_blocks) : b->nt_th;
+    if (persistent_blocks == 0) {
+        xcd_order(tf);
+        xcd_order(tt);
+    }
+    auto bad = [&](int code) {
+        if (b->ev_batch) (void)hipEventDestroy(b->ev_batch);
+        if (b->ev_dom) (void)hipEventDestroy(b->ev_dom);
+        if (b->owns_stream) (void)hipStreamDestroy(b->stream);
+        if (b->dptrs) (void)hipFree(b->dptrs);
+        if (b->dtiles_flow) (void)hipFree(b->dtiles_flow);
+        if (b->dtiles_th) (void)hipFree(b->dtiles_th);
+        delete b;
+        return code;
+    };
+    // graphs cannot be captured on the legacy null stream: use an own stream,
+    // ordered against the members' streams with events in pb_batch_step
+    if (!b->stream) {
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
+            return bad(fail(PB_EDEVICE, "stream creation failed"));
+        b->owns_stream = true;
+    }
+    if (hipEventCreateWithFlags(&b->ev_batch, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_dom, hipEventDisableTiming) != hipSuccess)
+        return bad(fail(PB_EDEVICE, "event creation failed"));
+    if (hipMalloc((void **)&b->dptrs, n * sizeof(void *)) != hipSuccess ||
+        hipMalloc((void **)&b->dtiles_flow, tf.size() * sizeof(PbTile)) != hipSuccess ||
+        hipMalloc((void **)&b->dtiles_th, tt.size() * sizeof(PbTile)) != hipSuccess)
+        return bad(fail(PB_ENOMEM, "batch tables allocation failed"));
+    for (int j = 0; j < n; ++j)
+        if (hipStreamSynchronize(doms[j]->stream) != hipSuccess) return bad(fail(PB_EDEVICE, "sync failed"));
+    if (hipMemcpy(b->dptrs, ptrs.data(), n * sizeof(void *), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->dtiles_flow, tf.data(), tf.size() * sizeof(PbTile), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->dtiles_th, tt.data(), tt.size() * sizeof(PbTile), hipMemcpyHostToDevice) != hipSuccess)
+        return bad(fail(PB_EDEVICE, "batch tables upload failed"));
+    *out = b;
+    return PB_OK;
+}
+
+static int batch_enqueue(pb_batch *b, int nsteps) {
+    const PbDesc *const *dp = (const PbDesc *const *)b->dptrs;
+    const int nd = (int)b->doms.size();
+    for (int k = 0; k < nsteps; ++k) {
+        PB_HIP(pb_launch_flow(b->prec, PB_MODE_STEP, b->fvar, dp, b->dtiles_flow, b->nt_flow, b->grid_flow, k, b->stream));
+        PB_HIP(pb_launch_thermal(b->tvar, dp, b->dtiles_th, b->nt_th, b->grid_th, k, b->stream));
+        if (b->any_flux) PB_HIP(pb_launch_flux(dp, nd, k, b->stream));
+    }
+    PB_HIP(pb_launch_advance(b->dptrs, nd, nsteps, b->stream));
+    return PB_OK;
+}
+
+int pb_batch_step(pb_batch *b, int64_t n) {
+    if (!b) return fail(PB_EINVAL, "batch is NULL");
+    if (n < 0) return fail(PB_EINVAL, "n must be >= 0");
+    // descriptors must match the host mirrors before device-side advancing
+    b->any_flux = false;
+    for (pb_domain *d : b->doms) {
+        if (d->hd.fl_tb > d->hd.fl_ta && d->cfg.ny_solid >= 3) b->any_flux = true;
+    }
+    int rc;
+    // the batch stream starts after the work already queued on member streams
+    for (hipStream_t s : b->dom_streams) {
+        if (s == b->stream) continue;
+        PB_HIP(hipEventRecord(b->ev_dom, s));
+        PB_HIP(hipStreamWaitEvent(b->stream, b->ev_dom, 0));
+    }
+    while (n > 0) {
+        if (b->spg > 0 && n >= b->spg) {
+            if (!b->gexec) {
+                PB_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+                rc = batch_enqueue(b, b->spg);
+                hipGraph_t g = nullptr;
+                hipError_t e = hipStreamEndCapture(b->stream, &g);
+                if (rc) return rc;
+                if (e != hipSuccess) return fail(PB_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+                b->graph = g;
+                PB_HIP(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+            }
+            PB_HIP(hipGraphLaunch(b->gexec, b->stream));
+            for (pb_domain *d : b->doms) {
+                d->t += b->spg;
+                d->par ^= (b->spg & 1);
+                d->hd.t0 = d->t;
+                d->hd.par0 = d->par;
+            }
+            n -= b->spg;
+        } else {
+            const int m = (int)std::min<int64_t>(n, 1 << 20);
+            if ((rc = batch_enqueue(b, m))) return rc;
+            for (pb_domain *d : b->doms) {
+                d->t += m;
+                d->par ^= (m & 1);
+                d->hd.t0 = d->t;
+                d->hd.par0 = d->par;
+            }
+            n -= m;
+        }
+    }
+    // later work on the members' streams (reads, syncs, steps) waits for the batch
+    PB_HIP(hipEventRecord(b->ev_batch, b->stream));
+    for (hipStream_t s : b->dom_streams)
+        if (s != b->stream) PB_HIP(hipStreamWaitEvent(s, b->ev_batch, 0));
+    return PB_OK;
+}
+
+void pb_batch_destroy(pb_batch *b) {
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->ev_batch) (void)hipEventDestroy(b->ev_batch);
+    if (b->ev_dom) (void)hipEventDestroy(b->ev_dom);
+    if (b->owns_stream) (void)hipStreamDestroy(b->stream);
+    (void)hipFree(b->dptrs);
+    (void)hipFree(b->dtiles_flow);
+    (void)hipFree(b->dtiles_th);
+    delete b;
+}
+
+// --------------------------------------------------------- host EOS helpers
+int pb_eos_critical_temperature(double a, double b, double R, double *Tc) {
+    if (!Tc || !(a > 0) || !(b > 0) || !(R > 0)) return fail(PB_EINVAL, "need a, b, R > 0 and an output");
+    // a = 0.45724 R^2 Tc^2 / Pc and b = 0.0778 R Tc / Pc  =>  a / b = (0.45724/0.0778) R Tc
+    *Tc = (a / b) * 0.0778 / (0.45724 * R);
+    return PB_OK;
+}
+
+// Maxwell pair by Newton iteration on (v_L, v_V): equal pressure and equal
+// area (the integral of P dv between the two volumes equals P (v_V - v_L)),
+// started from the roots of P = (P_max + P_min)/2 between the spinodals.
+int pb_eos_coexistence(double a, double b, double R, double omega, double Tc, double T, double *rho_L, double *rho_V) {
+    if (!rho_L || !rho_V) return fail(PB_EINVAL, "outputs are NULL");
+    if (!(T > 0) || !(T < Tc) || !(a > 0) || !(b > 0) || !(R > 0)) return fail(PB_EINVAL, "need 0 < T < Tc and a, b, R > 0");
+    const double kap = 0.37464 + 1.54226 * omega - 0.26992 * omega * omega;
+    const double s = 1.0 + kap * (1.0 - std::sqrt(T / Tc));
+    const double A = a * s * s, r2 = std::sqrt(2.0);
+    // in specific volume v = 1/rho: P = R T/(v - b) - A/(v^2 + 2 b v - b^2)
+    auto P = [&](double v) { return R * T / (v - b) - A / (v * v + 2.0 * b * v - b * b); };
+    auto dP = [&](double v) {
+        const double q = v * v + 2.0 * b * v - b * b;
+        return -R * T / ((v - b) * (v - b)) + A * (2.0 * v + 2.0 * b) / (q * q);
+    };
+    auto I = [&](double v) {   // antiderivative of P dv
+        return R * T * std::log(v - b) - A / (2.0 * r2 * b) * std::log((v + b - r2 * b) / (v + b + r2 * b));
+    };
+    // spinodals: scan dP on a log grid of v
+    const int N = 4000;
+    double vmin_sp = 0, vmax_sp = 0;
+    double prev = dP(b * 1.0001);
+    bool got1 = false;
+    for (int k = 1; k <= N; ++k) {
+        const double v = b * std::exp(std::log(1.0001) + k * (std::log(1e4) / N));
+        const double cur = dP(v);
+        if (!got1 && prev < 0 && cur >= 0) { vmin_sp = v; got1 = true; }
+        else if (got1 && prev > 0 && cur <= 0) { vmax_sp = v; break; }
+        prev = cur;
+    }
+    if (!got1 || vmax_sp == 0) return fail(PB_EINVAL, "no two-phase region at this temperature");
+    // vmin_sp: liquid spinodal (local minimum of P), vmax_sp: vapour spinodal (local maximum)
+    const double pm = 0.5 * (std::max(P(vmin_sp), 0.0) + P(vmax_sp));
+    auto root = [&](double lo, double hi) {   // P(v) = pm on a monotone bracket
+        for (int it = 0; it < 200; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if ((P(mid) - pm) * (P(lo) - pm) > 0) lo = mid; else hi = mid;
+        }
+        return 0.5 * (lo + hi);
+    };
+    double vl = root(b * 1.0001, vmin_sp);
+    double vv = root(vmax_sp, b * 1e5);
+    for (int it = 0; it < 100; ++it) {
+        const double F1 = P(vl) - P(vv);
+        const double F2 = I(vv) - I(vl) - P(vl) * (vv - vl);
+        const double J11 = dP(vl), J12 = -dP(vv);
+        const double J21 = -dP(vl) * (vv - vl), J22 = P(vv) - P(vl);
+        const double det = J11 * J22 - J12 * J21;
+        if (det == 0.0) break;
+        const double dl = (F1 * J22 - J12 * F2) / det, dv = (J11 * F2 - J21 * F1) / det;
+        vl -= dl;
+        vv -= dv;
+        if (std::fabs(dl) < 1e-15 * vl && std::fabs(dv) < 1e-15 * vv) break;
+    }
+    if (!(vl > b) || !(vv > vl)) return fail(PB_EINVAL, "coexistence iteration failed");
+    *rho_L = 1.0 / vl;
+    *rho_V = 1.0 / vv;
+    return PB_OK;
+}
+
+int pb_eos_psi(double a, double b, double R, double omega, double Tc, double G, double rho, double T, double *psi) {
+    if (!psi || !(G < 0) || !(rho > 0) || !(T > 0) || !(Tc > 0) || !(rho * b < 1.0))
+        return fail(PB_EINVAL, "need psi output, G < 0, 0 < rho < 1/b, T, Tc > 0");
+    const double kap = 0.37464 + 1.54226 * omega - 0.26992 * omega * omega;
+    const double s = 1.0 + kap * (1.0 - std::sqrt(T / Tc));
+    const double P = rho * R * T / (1.0 - b * rho) - a * s * s * rho * rho / (1.0 + 2.0 * b * rho - b * b * rho * rho);
+    const double rad = 2.0 * (P - rho / 3.0) / G;
+    if (!(rad >= 0.0)) return fail(PB_EINVAL, "negative psi radicand at rho = %g, T = %g", rho, T);
+    *psi = std::sqrt(rad);
+    return PB_OK;
+}
+
+}  // extern "C"

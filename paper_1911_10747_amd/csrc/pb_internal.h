@@ -1,0 +1,64 @@
+// Internal structures shared by the host API (pb_api.cpp) and the kernels
+// (pb_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+// Per-domain descriptor read by every kernel (one per domain of a launch).
+// Buffers come in A/B pairs; step k of a launch sequence reads buffer
+// (par0 + k) & 1 and writes the other.  t = t0 + k.
+struct PbDesc {
+    // geometry
+    int32_t nx, nyf, nys, nr, pitch;
+    uint32_t flags;
+    int32_t par0;
+    int32_t pad0;
+    int64_t t0;
+    int64_t fl_ta, fl_tb;
+    int32_t fl_every;
+    int32_t pad1;
+    // state
+    void *f[2];          // populations [9][nyf][pitch], double or float (deviation)
+    double *rho[2];      // rho(t) written by the flow kernel, [nyf][pitch]
+    double *vx, *vy;     // v(t) written by the flow kernel, [nyf][pitch]
+    double *T[2];        // temperature [nr][pitch]
+    // boundary data [nx]
+    const double *Tb, *Tb_alt, *gbot, *gtop;
+    int64_t alt_t0, alt_t1;
+    double T_top;
+    // diagnostics
+    int32_t *err;        // sticky non-finite flag
+    double *flux;        // [8]: q_bot, q_top, Tw (inst), their sums, count
+    // read-back staging (FP64, [9][nyf][pitch] + 3 x [nyf][pitch])
+    double *rd_f, *rd_rho, *rd_vx, *rd_vy;
+    // constants
+    double a, b, R, kappa, Tc, sqrtTc, inv_sqrtTc, G;
+    double s_e, s_q, varpi;
+    double tau_V, rho_V, ktau;   // tau(rho) = tau_V + (rho - rho_V) * ktau  (Eq. 5)
+    double g, rho_bar;
+    double Cv, Cvchi, rho_S, C_S, lambda_S;
+};
+
+struct PbTile {
+    int32_t dom, x0, y0, pad;
+};
+
+enum { PB_MODE_STEP = 0, PB_MODE_READ = 1 };
+
+// Launch helpers implemented in pb_kernels.hip.  All return hipError_t.
+// prec: 0 = FP64 storage, 1 = FP32 deviation storage.
+// d_descs is a device array of device pointers to the domains' descriptors.
+hipError_t pb_launch_flow(int prec, int mode, int tile_variant, const PbDesc *const *d_descs, const PbTile *d_tiles,
+                          int ntiles, int grid, int k, hipStream_t s);
+hipError_t pb_launch_thermal(int tile_variant, const PbDesc *const *d_descs, const PbTile *d_tiles, int ntiles,
+                             int grid, int k, hipStream_t s);
+hipError_t pb_launch_flux(const PbDesc *const *d_descs, int ndom, int k, hipStream_t s);
+hipError_t pb_launch_advance(PbDesc *const *d_descs, int ndom, int nsteps, hipStream_t s);
+hipError_t pb_launch_init(int prec, const PbDesc *d_desc, int par, hipStream_t s);
+
+// Tile geometry of the variants (x, y extents of one block's tile).
+void pb_flow_tile_shape(int variant, int *bx, int *by);
+void pb_thermal_tile_shape(int variant, int *bx, int *by);
+int pb_flow_variants();
+int pb_thermal_variants();

@@ -1,0 +1,88 @@
+"""Configurations and seeded initial states for pool-boiling jobs.
+
+Derived constants (Tc, Maxwell densities, psi at the liquid density) come from
+the library's host EOS helpers; inputs (layouts, hot spots) from the seeded
+generators in `workloads`.  Nothing here steps the method.
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+import workloads as W
+
+from . import poolboil as pb
+
+
+@dataclass
+class Derived:
+    Tc: float
+    Tsat: float
+    rho_L: float
+    rho_V: float
+    psi_L: float
+
+
+def derived(a=None, b=None, R=None, omega=None, G=-1.0, t_ratio=W.T_SAT_OVER_TC):
+    P = W.BASE_PARAMS
+    a = P["a"] if a is None else a
+    b = P["b"] if b is None else b
+    R = P["R"] if R is None else R
+    omega = P["omega"] if omega is None else omega
+    Tc = pb.critical_temperature(a, b, R)
+    Ts = t_ratio * Tc
+    rl, rv = pb.coexistence(a, b, R, omega, Tc, Ts)
+    return Derived(Tc, Ts, rl, rv, pb.eos_psi(a, b, R, omega, Tc, G, rl, Ts))
+
+
+@dataclass
+class JobSpec:
+    """One boiling-curve job: a domain size, a heater-bottom superheat (units
+    of Tc), a number of steps and a seed for the nucleate hot spots."""
+    nx: int
+    nyf: int
+    nys: int
+    superheat: float
+    steps: int = 2000
+    seed: int = 0
+    precision: int = pb.PB_FP32_DEV
+    spots_per_columns: int = 64      # one +2% hot spot per this many columns (at least one)
+    liquid_fraction: float = 0.4     # liquid below this fraction of the fluid height
+    gamma_frac: float = 0.7          # wall adhesion gamma = -gamma_frac * psi_L
+    tile: tuple = (0, 0)
+    thermal_tile: int = 0
+    flux_every: int = 10
+    overrides: dict = field(default_factory=dict)
+
+
+def make_config(spec, d=None):
+    d = derived() if d is None else d
+    P = dict(W.BASE_PARAMS)
+    P.update({k: v for k, v in spec.overrides.items() if k in P})
+    return pb.make_config(nx=spec.nx, ny_fluid=spec.nyf, ny_solid=spec.nys, precision=spec.precision, flags=0,
+                          tile_x=spec.tile[0], tile_y=spec.tile[1], thermal_tile=spec.thermal_tile,
+                          Tc=d.Tc, rho_L=d.rho_L, rho_V=d.rho_V, rho_S=W.RHO_S_OVER_RHO_L * d.rho_L, **P)
+
+
+def initial_state(spec, d=None):
+    """(bc kwargs, rho, T) of the standard pool-boiling start."""
+    d = derived() if d is None else d
+    Tb = d.Tsat + spec.superheat * d.Tc
+    n_spots = max(1, spec.nx // spec.spots_per_columns)
+    Tb_row = W.spot_Tb(spec.nx, Tb, n_spots, spec.seed)
+    gam = np.full(spec.nx, -spec.gamma_frac * d.psi_L)
+    bc = dict(T_top=d.Tsat, Tb=Tb_row, gamma_bot=gam, gamma_top=gam.copy())
+    rho = W.layered_rho(spec.nx, spec.nyf, int(round(spec.liquid_fraction * spec.nyf)), d.rho_L, d.rho_V)
+    T = W.thermal_init(spec.nx, spec.nys, spec.nyf, d.Tsat, Tb_row)
+    return bc, rho, T
+
+
+def make_domain(spec, d=None, use_torch=True, stream=None, with_window=True):
+    d = derived() if d is None else d
+    dom = pb.Domain(make_config(spec, d), use_torch=use_torch, stream=stream)
+    bc, rho, T = initial_state(spec, d)
+    dom.set_bc(**bc)
+    dom.set_fields(rho, T)
+    if with_window and spec.nys >= 3:
+        # Eq. 38 time mean over the second half of the run
+        dom.flux_window(spec.steps // 2, spec.steps + 1, spec.flux_every)
+    return dom

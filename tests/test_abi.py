@@ -1,0 +1,67 @@
+"""The C-ABI library loads on a machine without a GPU and exports every symbol
+that include/poolboil.h declares; host-only helpers work there."""
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+from helpers import derived
+import workloads as W
+
+HEADER = os.path.join(ROOT, "include", "poolboil.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pb_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1911_10747_amd import poolboil as pb
+    names = declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(pb.lib, n), n
+    assert sorted(pb.EXPORTED) == names
+    assert pb.lib.pb_version() == 1
+
+
+def test_config_struct_matches_header_field_order():
+    from paper_1911_10747_amd import poolboil as pb
+    src = open(HEADER).read()
+    body = src[src.index("typedef struct pb_config"):src.index("} pb_config;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = []
+    for decl in re.findall(r"(?:int32_t|uint32_t|double)\s+([^;]+);", body):
+        fields += [f.strip() for f in decl.split(",")]
+    assert fields == [f for f, _ in pb.Config._fields_]
+
+
+def test_host_eos_helpers_match_oracle():
+    """The library's own Tc formula and Newton-based Maxwell construction agree
+    with the oracle's independent bisection construction."""
+    from paper_1911_10747_amd import poolboil as pb
+    P = W.BASE_PARAMS
+    for a in (2 / 49, 3 / 49):
+        d = derived(a, P["b"], P["R"], P["omega"])
+        Tc = pb.critical_temperature(a, P["b"], P["R"])
+        assert Tc == pytest.approx(d["Tc"], rel=1e-14)
+        rl, rv = pb.coexistence(a, P["b"], P["R"], P["omega"], Tc, 0.86 * Tc)
+        assert rl == pytest.approx(d["rho_L"], rel=1e-10)
+        assert rv == pytest.approx(d["rho_V"], rel=1e-10)
+
+
+def test_invalid_configs_rejected_without_gpu():
+    """Validation happens on the host before any device call."""
+    from paper_1911_10747_amd import poolboil as pb
+    P = dict(W.BASE_PARAMS, Tc=0.07, rho_L=6.5, rho_V=0.38, rho_S=19.5)
+    base = dict(nx=8, ny_fluid=8, ny_solid=4, **P)
+    for bad in (dict(nx=0), dict(ny_solid=0), dict(precision=7), dict(flags=0x100), dict(G=1.0),
+                dict(tile_x=48, tile_y=3), dict(thermal_tile=99), dict(rho_V=7.0), dict(s_e=2.5)):
+        cfg = pb.make_config(**dict(base, **bad))
+        with pytest.raises(pb.PbError) as ei:
+            pb.domain_bytes(cfg)
+        assert ei.value.code == pb.PB_EINVAL
+    assert pb.domain_bytes(pb.make_config(**base)) > 0

@@ -1,0 +1,196 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Tolerances (max-norm relative error per field, err = max|X_gpu - X_orc| /
+max|X_orc| over rho, T and f, and over u_x, u_y with the speed scale
+max(|u_x|, |u_y|) as denominator): 1e-11 for FP64 storage and 2e-5 for
+FP32-deviation storage, over a 200-step window; bit-identity where the
+arithmetic per node is the same by construction (tile shape, batching,
+checkpoint/resume in FP64).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_common import compare, gpu_domain, oracle_domain, pb_config, run_pair
+from helpers import params, pool_case
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")  # import at collection, outside per-test time limits
+
+TOL = {0: 1e-11, 1: 2e-5}
+
+
+def _report(name, errs):
+    print(name, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_pool_boiling_100x100_200_steps(precision):
+    """Plain pool boiling, 100x100 fluid over a 100x10 heater, liquid below
+    y = 40, heater bottom at Tsat + 0.1 Tc with 4 seeded +2% spots."""
+    P, d, bc, rho, T = pool_case(100, 100, 10, superheat=0.1, n_spots=4, seed=0, y0=40)
+    g, o = run_pair(P, bc, rho, T, steps=200, precision=precision, window=(50, 201, 10))
+    errs = compare(g, o)
+    _report(f"C0 prec={precision}", errs)
+    assert all(v <= TOL[precision] for v in errs.values()), errs
+    for k in ("q_bottom_mean", "q_top_mean", "T_w_mean", "q_bottom_inst"):
+        assert g["flux"][k] == pytest.approx(o["flux"][k], rel=TOL[precision] * 10, abs=1e-15), k
+    assert g["flux"]["n_samples"] == o["flux"]["n_samples"] == 16
+
+
+def test_ragged_domain_and_tile_shapes_are_bit_identical():
+    """77x45 fluid over 5 heater rows (ragged against every tile shape): the
+    result matches the oracle and is bit-identical for every flow and
+    thermal tile variant."""
+    from paper_1911_10747_amd import poolboil as pb
+    P, d, bc, rho, T = pool_case(77, 45, 5, superheat=0.2, n_spots=3, seed=7, y0=17)
+    ref = None
+    shapes = [(64, 4), (64, 8), (32, 8), (128, 4), (32, 16), (64, 16)]
+    for i, tile in enumerate(shapes):
+        g = gpu_domain(P, bc, rho, T, 0, tile=tile, thermal_tile=i % 4)
+        g.step(120)
+        g.sync()
+        r = g.read()
+        g.close()
+        if ref is None:
+            ref = r
+            o = oracle_domain(P, bc, rho, T)
+            o.step(120)
+            errs = compare(r, o.read())
+            _report("ragged", errs)
+            assert all(v <= 1e-11 for v in errs.values()), errs
+        else:
+            for k in ("rho", "ux", "uy", "T", "f"):
+                np.testing.assert_array_equal(r[k], ref[k], err_msg=f"{k} differs for tile {tile}")
+
+
+@pytest.mark.parametrize("isothermal", [1, 0])
+def test_periodic_drop(isothermal):
+    """Fully periodic box with a drop (no walls, no heater): exercises the
+    periodic wrap in y of streaming, forces and the thermal stencil."""
+    nx, ny = 48, 40
+    P, d = params(nx, ny, 0, periodic_y=1, isothermal=isothermal, g=0.0)
+    rho = W.drop_rho(nx, ny, 9.0, d["rho_L"], d["rho_V"], width=3.0, cx=20.3, cy=17.6)
+    T = W.perturbed(np.full((ny, nx), d["Tsat"]), 0.02, 11)
+    bc = dict(T_top=d["Tsat"])
+    g, o = run_pair(P, bc, rho, T, steps=200, precision=0)
+    errs = compare(g, o)
+    _report(f"drop iso={isothermal}", errs)
+    assert all(v <= 1e-11 for v in errs.values()), errs
+
+
+def test_frozen_flow_conduction():
+    """Frozen flow (conduction only) through heater and liquid."""
+    nx, nyf, nys = 5, 6, 5
+    P, d = params(nx, nyf, nys, frozen_flow=1)
+    Tb = W.spot_Tb(nx, d["Tsat"] + 0.1 * d["Tc"], 1, 2)
+    bc = dict(T_top=d["Tsat"], Tb=Tb)
+    rho = W.layered_rho(nx, nyf, 3, d["rho_L"], d["rho_V"])
+    T = W.thermal_init(nx, nys, nyf, d["Tsat"], Tb)
+    g, o = run_pair(P, bc, rho, T, steps=300, precision=0, window=(1, 301, 1))
+    errs = compare(g, o)
+    _report("frozen", errs)
+    assert all(v <= 1e-11 for v in errs.values()), errs
+    assert g["flux"]["q_bottom_mean"] == pytest.approx(o["flux"]["q_bottom_mean"], rel=1e-11)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 3), (2, 3, 3), (3, 70, 4), (130, 2, 3)])
+def test_degenerate_shapes(shape):
+    """Single column, two-row fluid, tall-thin and wide-flat domains."""
+    nx, nyf, nys = shape
+    P, d, bc, rho, T = pool_case(nx, nyf, nys, superheat=0.15, n_spots=0, y0=max(1, nyf // 2))
+    g, o = run_pair(P, bc, rho, T, steps=60, precision=0)
+    errs = compare(g, o)
+    _report(f"shape {shape}", errs)
+    assert all(v <= 1e-11 for v in errs.values()), errs
+
+
+def test_bottom_window_and_zero_steps():
+    """Section 3.2 trigger window on the heater bottom; step(0) is a no-op."""
+    nx, nyf, nys = 40, 30, 4
+    P, d, bc, rho, T = pool_case(nx, nyf, nys, superheat=0.1, n_spots=0)
+    bc = dict(bc, Tb_alt=W.sinus_Tb(nx, bc["Tb"][0], 0.02 * d["Tc"], 20.0), t0=5, t1=25)
+    g = gpu_domain(P, bc, rho, T)
+    o = oracle_domain(P, bc, rho, T)
+    g.step(0)
+    for n in (3, 7, 20):
+        g.step(n)
+        o.step(n)
+        errs = compare(g.read(), o.read())
+        assert all(v <= 1e-11 for v in errs.values()), (n, errs)
+    assert g.t == o.t == 30
+    g.close()
+
+
+def test_checkpoint_resume_fp64_bit_exact():
+    """read f(t), T(t) and rho_bar, restore into a fresh domain, continue:
+    identical to the uninterrupted run."""
+    P, d, bc, rho, T = pool_case(50, 40, 5, superheat=0.2, n_spots=2, seed=4)
+    a = gpu_domain(P, bc, rho, T)
+    a.step(40)
+    s = a.read()
+    a.step(40)
+    ra = a.read()
+    b = gpu_domain(P, bc, rho, T)
+    b.set_state(s["f"], s["T"], 40, a.rho_bar)
+    b.step(40)
+    rb = b.read()
+    assert b.t == 80
+    for k in ("rho", "ux", "uy", "T", "f"):
+        np.testing.assert_array_equal(ra[k], rb[k], err_msg=k)
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_matches_alone_bit_exact(precision):
+    """Three uneven domains stepped in shared launches (eager and replayed
+    from a captured graph) equal each domain stepped alone, bit for bit."""
+    from paper_1911_10747_amd import poolboil as pb
+    cases = [pool_case(70, 50, 4, superheat=0.08, seed=1), pool_case(33, 20, 3, superheat=0.25, seed=2),
+             pool_case(130, 64, 7, superheat=0.15, seed=3)]
+    alone = []
+    for P, d, bc, rho, T in cases:
+        g = gpu_domain(P, bc, rho, T, precision)
+        g.flux_window(10, 1000, 5)
+        g.step(46)
+        g.sync()
+        alone.append((g.read(), g.heat_flux()))
+        g.close()
+    doms = []
+    for P, d, bc, rho, T in cases:
+        g = gpu_domain(P, bc, rho, T, precision)
+        g.flux_window(10, 1000, 5)
+        doms.append(g)
+    batch = pb.Batch(doms, steps_per_graph=10)
+    batch.step(3)     # eager
+    batch.step(43)    # 4 graph replays + 3 eager
+    for g in doms:
+        g.sync()
+    for g, (r0, f0) in zip(doms, alone):
+        assert g.t == 46
+        r = g.read()
+        for k in ("rho", "ux", "uy", "T", "f"):
+            np.testing.assert_array_equal(r[k], r0[k], err_msg=k)
+        assert g.heat_flux() == f0
+    batch.close()
+    for g in doms:
+        g.close()
+
+
+def test_nonfinite_flag_is_sticky():
+    """A density at the EOS pole region (rho b close to 1) makes the psi
+    radicand negative: the step completes and pb_sync reports PB_ENONFINITE."""
+    from paper_1911_10747_amd import poolboil as pb
+    P, d, bc, rho, T = pool_case(20, 12, 3, n_spots=0)
+    rho = rho.copy()
+    rho[2, 5] = 10.0
+    g = gpu_domain(P, bc, rho, T)
+    g.step(2)
+    with pytest.raises(pb.NonFiniteError):
+        g.sync()
+    g.set_fields(*pool_case(20, 12, 3, n_spots=0)[3:5])
+    g.step(2)
+    g.sync()
+    g.close()
