@@ -92,6 +92,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default="0x0")
     ap.add_argument("--thermal-tile", type=int, default=0)
+    ap.add_argument("--no-tune", action="store_true", help="skip the tile autotuner; use --tile/--thermal-tile")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -104,9 +105,16 @@ def main():
 
     nx, nyf, nys, prec, desc = WORKLOADS[args.workload]
     tx, ty = (int(v) for v in args.tile.split("x"))
-    spec = presets.JobSpec(nx=nx, nyf=nyf, nys=nys, superheat=0.1, steps=args.warmup + args.steps, seed=0,
-                           precision=prec, tile=(tx, ty), thermal_tile=args.thermal_tile)
+    thermal_tile = args.thermal_tile
     torch.cuda.set_device(0)
+    tuned = None
+    if not args.no_tune:
+        from paper_1911_10747_amd import autotune
+        tuned = autotune.tune(nx, nyf, nys, prec, use_cache=False,
+                              log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
+        (tx, ty), thermal_tile = tuned["tile"], tuned["thermal_tile"]
+    spec = presets.JobSpec(nx=nx, nyf=nyf, nys=nys, superheat=0.1, steps=args.warmup + args.steps, seed=0,
+                           precision=prec, tile=(tx, ty), thermal_tile=thermal_tile)
     dom = presets.make_domain(spec)
     dom.flux_window(0, 1 << 62, 10)
     print(f"bench: {args.workload} {nx}x{nyf}+{nys} prec={prec}: warmup {args.warmup}", file=sys.stderr, flush=True)
@@ -140,7 +148,8 @@ def main():
         "data": "synthetic (seeded pool-boiling start: Maxwell liquid layer, +2% heater hot spots)",
         "config": {"workload": desc, "nx": nx, "ny_fluid": nyf, "ny_solid": nys,
                    "storage": "fp32-deviation" if prec else "fp64", "arithmetic": "fp64",
-                   "tile": [tx, ty], "thermal_tile": args.thermal_tile, "parallelism": "single GPU"},
+                   "tile": [tx, ty], "thermal_tile": thermal_tile, "autotuned": tuned is not None,
+                   "parallelism": "single GPU"},
         "roofline": {
             "bound": "hbm",
             "kernel": "one step = k_flow + k_thermal (algorithmic bytes of the whole step over the summed "

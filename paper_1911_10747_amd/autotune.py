@@ -1,0 +1,75 @@
+"""Tile autotuner for the flow and thermal kernels.
+
+The two launches of a step are independent in their tiling, so each is tuned
+on its own: every flow tile shape is timed with the default thermal variant and
+every thermal variant with the default flow tile, using HIP events around each
+launch (pb_profile_steps).  Results are cached per (nx, ny_fluid, ny_solid,
+precision) in a JSON file.  Tiling never changes results: per-node arithmetic
+is the same for every variant (checked bit for bit by the GPU tests).
+"""
+import json
+import os
+
+from . import poolboil as pb
+from . import presets
+
+FLOW_TILES = [(64, 4), (64, 8), (32, 8), (128, 4), (32, 16), (64, 16)]
+THERMAL_VARIANTS = list(range(4))
+CACHE = os.environ.get("POOLBOIL_TUNE_CACHE", os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                            "tune_cache.json"))
+
+
+def _key(nx, nyf, nys, precision):
+    return f"{nx}x{nyf}+{nys}:p{precision}"
+
+
+def load_cache():
+    if os.path.exists(CACHE):
+        with open(CACHE) as fh:
+            return json.load(fh)
+    return {}
+
+
+def save_cache(c):
+    tmp = CACHE + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(c, fh, indent=1, sort_keys=True)
+    os.replace(tmp, CACHE)
+
+
+def _time(spec, steps, warmup):
+    dom = presets.make_domain(spec, with_window=False)
+    dom.step(warmup)
+    prof = dom.profile_steps(steps)
+    dom.close()
+    return prof
+
+
+def tune(nx, nyf, nys, precision=pb.PB_FP32_DEV, steps=30, warmup=5, use_cache=True, log=None):
+    """Return dict(tile=(bx, by), thermal_tile=v, flow_ms=..., thermal_ms=...)."""
+    key = _key(nx, nyf, nys, precision)
+    cache = load_cache() if use_cache else {}
+    if key in cache:
+        r = cache[key]
+        r["tile"] = tuple(r["tile"])
+        return r
+    base = dict(nx=nx, nyf=nyf, nys=nys, superheat=0.1, precision=precision, steps=steps + warmup)
+    flow = {}
+    for tile in FLOW_TILES:
+        flow[tile] = _time(presets.JobSpec(tile=tile, **base), steps, warmup)["flow_ms"]
+        if log:
+            log(f"autotune {key} flow tile {tile}: {flow[tile]:.4f} ms")
+    best_tile = min(flow, key=flow.get)
+    therm = {}
+    for v in THERMAL_VARIANTS:
+        therm[v] = _time(presets.JobSpec(tile=best_tile, thermal_tile=v, **base), steps, warmup)["thermal_ms"]
+        if log:
+            log(f"autotune {key} thermal variant {v}: {therm[v]:.4f} ms")
+    best_v = min(therm, key=therm.get)
+    r = dict(tile=best_tile, thermal_tile=best_v, flow_ms=flow[best_tile], thermal_ms=therm[best_v],
+             flow_all={f"{a}x{b}": v for (a, b), v in flow.items()}, thermal_all={str(k): v for k, v in therm.items()})
+    if use_cache:
+        cache = load_cache()
+        cache[key] = dict(r, tile=list(best_tile))
+        save_cache(cache)
+    return r

@@ -334,6 +334,7 @@ int pb_create_domain(const pb_config *cfg, void *stream, void *dev_mem, size_t d
     h.sqrtTc = std::sqrt(cfg->Tc);
     h.inv_sqrtTc = 1.0 / h.sqrtTc;
     h.G = cfg->G;
+    h.invG = 1.0 / cfg->G;
     h.s_e = cfg->s_e;
     h.s_q = cfg->s_q;
     h.varpi = cfg->varpi;

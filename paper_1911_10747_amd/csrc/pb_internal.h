@@ -33,7 +33,7 @@ struct PbDesc {
     // read-back staging (FP64, [9][nyf][pitch] + 3 x [nyf][pitch])
     double *rd_f, *rd_rho, *rd_vx, *rd_vy;
     // constants
-    double a, b, R, kappa, Tc, sqrtTc, inv_sqrtTc, G;
+    double a, b, R, kappa, Tc, sqrtTc, inv_sqrtTc, G, invG;
     double s_e, s_q, varpi;
     double tau_V, rho_V, ktau;   // tau(rho) = tau_V + (rho - rho_V) * ktau  (Eq. 5)
     double g, rho_bar;

@@ -43,27 +43,59 @@ __device__ __forceinline__ int wrap_once(int v, int n) {
     return v;
 }
 
-__device__ __forceinline__ void flag_error(const PbDesc &d) { atomicOr(d.err, 1); }
+// Address-space views: descriptors are read through the constant space
+// (scalar loads), field arrays through the global space.
+#define PB_CAS __attribute__((address_space(4)))
+#define PB_GAS __attribute__((address_space(1)))
+typedef const PbDesc PB_CAS cdesc;
 
-// Eq. 13 and Eq. 12 (c = 1, c_s^2 = 1/3); sets bad on a negative radicand.
-__device__ __forceinline__ double eos_psi(const PbDesc &d, double rho, double T, bool &bad) {
-    const double st = sqrt(T) * d.inv_sqrtTc;          // sqrt(T / Tc)
-    const double s = 1.0 + d.kappa * (1.0 - st);
-    const double br = d.b * rho;
-    const double P = rho * d.R * T / (1.0 - br) - d.a * (s * s) * rho * rho / (1.0 + 2.0 * br - br * br);
-    const double rad = 2.0 * (P - rho * (1.0 / 3.0)) / d.G;
-    bad = bad || !(rad >= 0.0);
-    return sqrt(rad);
+template <typename T>
+__device__ __forceinline__ const T PB_GAS *gcast(const void *p) { return (const T PB_GAS *)p; }
+template <typename T>
+__device__ __forceinline__ T PB_GAS *gcast_w(void *p) { return (T PB_GAS *)p; }
+
+__device__ __forceinline__ void flag_error(cdesc &d) { atomicOr(d.err, 1); }
+
+// reciprocal and square root from the hardware approximations refined by
+// Newton steps (within about one ulp of the correctly rounded values)
+__device__ __forceinline__ double frcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return r;
+}
+__device__ __forceinline__ double fsqrt(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * y, g = x * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double e = fma(-g, g, x);
+    g = fma(e, h, g);
+    return x == 0.0 ? 0.0 : g;   // negative x gives NaN through rsq
 }
 
-// Pull f_i(x, y, t) = f*_i(x - e_i, t-1), halfway bounce-back at the walls.
-// FP32 deviation storage rebuilds f* = w_i rho_ref + delta with rho_ref the
-// density of the node the value was stored at.
+// Eq. 13 and Eq. 12 (c = 1, c_s^2 = 1/3) with a single division; sets bad on a
+// negative radicand.
+__device__ __forceinline__ double eos_psi(cdesc &d, double rho, double T, bool &bad) {
+    const double st = fsqrt(T) * d.inv_sqrtTc;          // sqrt(T / Tc)
+    const double s = 1.0 + d.kappa * (1.0 - st);
+    const double br = d.b * rho;
+    const double den1 = 1.0 - br, den2 = 1.0 + 2.0 * br - br * br;
+    const double P = (rho * d.R * T * den2 - d.a * (s * s) * rho * rho * den1) * frcp(den1 * den2);
+    const double rad = 2.0 * (P - rho * (1.0 / 3.0)) * d.invG;
+    bad = bad || !(rad >= 0.0);
+    return fsqrt(rad);
+}
+
+// Pull f_i(x, y, t) = f*_i(x - e_i, t-1), halfway bounce-back at the walls
+// (general path, any node).  FP32 deviation storage rebuilds
+// f* = w_i rho_ref + delta with rho_ref the density of the node the value was
+// stored at.
 template <typename FT>
-__device__ __forceinline__ void pull_node(const PbDesc &d, const FT *__restrict__ fin,
-                                          const double *__restrict__ rin, int x, int y, bool pery,
-                                          double f[9]) {
-    const size_t plane = (size_t)d.nyf * d.pitch;
+__device__ __forceinline__ void pull_node(cdesc &d, const FT PB_GAS *fin, const double PB_GAS *rin, int x, int y,
+                                          bool pery, double f[9]) {
+    const uint32_t plane = (uint32_t)d.nyf * (uint32_t)d.pitch;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         int xs = wrap_once(x - kEX[i], d.nx);
@@ -76,8 +108,8 @@ __device__ __forceinline__ void pull_node(const PbDesc &d, const FT *__restrict_
             xs = x;
             ys = y;
         }
-        const size_t idx = (size_t)ys * d.pitch + xs;
-        const FT v = fin[(size_t)ii * plane + idx];
+        const uint32_t idx = (uint32_t)ys * (uint32_t)d.pitch + (uint32_t)xs;
+        const FT v = fin[(uint32_t)ii * plane + idx];
         if constexpr (std::is_same<FT, float>::value)
             f[i] = kW[i] * rin[idx] + (double)v;
         else
@@ -85,350 +117,422 @@ __device__ __forceinline__ void pull_node(const PbDesc &d, const FT *__restrict_
     }
 }
 
+// Same pull for a node whose nine sources are all inside the fluid and away
+// from the x edges: constant offsets, no branches.
 template <typename FT>
-__device__ __forceinline__ void store_pop(FT *__restrict__ fout, size_t plane, size_t idx, int i, double fs,
+__device__ __forceinline__ void pull_inner(const FT PB_GAS *fin, const double PB_GAS *rin, uint32_t plane,
+                                           uint32_t pitch, uint32_t idx, double f[9]) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const uint32_t src = idx - (uint32_t)(kEY[i] * (int)pitch) - (uint32_t)kEX[i];
+        const FT v = (fin + (uint32_t)i * plane)[src];
+        if constexpr (std::is_same<FT, float>::value)
+            f[i] = kW[i] * rin[src] + (double)v;
+        else
+            f[i] = v;
+    }
+}
+
+template <typename FT>
+__device__ __forceinline__ void store_pop(FT PB_GAS *fout, uint32_t plane, uint32_t idx, int i, double fs,
                                           double rho) {
     if constexpr (std::is_same<FT, float>::value)
-        fout[(size_t)i * plane + idx] = (float)(fs - kW[i] * rho);
+        (fout + (uint32_t)i * plane)[idx] = (float)(fs - kW[i] * rho);
     else
-        fout[(size_t)i * plane + idx] = fs;
+        (fout + (uint32_t)i * plane)[idx] = fs;
 }
 
 // ---------------------------------------------------------------- flow step
+// One tile: psi over the tile plus a one-node ring in LDS, then forces,
+// velocity and collision on the tile.  INNER: every node of the tile and its
+// ring is at least two nodes from the x edges and from the walls.
+template <typename FT, int BX, int BY, int MODE, bool INNER>
+__device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, double *s_psi, int *s_bad) {
+    constexpr int LW = BX + 2, LH = BY + 2;
+    constexpr int NHALO = 2 * LW + 2 * BY;
+    const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
+    const bool pery = (d.flags & F_PERY) != 0;
+    const bool frozen = (d.flags & F_FROZEN) != 0;
+    const int pin = (int)((d.par0 + k) & 1), pout = pin ^ 1;
+    const FT PB_GAS *fin = gcast<FT>(d.f[pin]);
+    const double PB_GAS *rin = gcast<double>(d.rho[pin]);
+    const double PB_GAS *Tt = gcast<double>(d.T[pin]);
+    const uint32_t pitch = (uint32_t)d.pitch, plane = (uint32_t)d.nyf * pitch;
+    const uint32_t toff = (uint32_t)d.nys * pitch;           // fluid row 0 in the T array
+    bool bad = false;
+
+    // this thread's node; positions past the edge wrap once so that the first
+    // column/row beyond holds the periodic neighbour
+    const int xr = te.x0 + tx, yr = te.y0 + ty;
+    const bool own = INNER || (xr < d.nx && yr < d.nyf);
+    const int xw = INNER ? xr : xr - (xr >= d.nx ? d.nx : 0);
+    const int yw = (INNER || !pery) ? yr : yr - (yr >= d.nyf ? d.nyf : 0);
+    const bool live = INNER || (xw < d.nx && yw < d.nyf);
+    double f[9], rho = 0.0, jx = 0.0, jy = 0.0, psi = 0.0;
+    const uint32_t idx = (uint32_t)yw * pitch + (uint32_t)xw;
+    if (live) {
+        if (INNER) pull_inner<FT>(fin, rin, plane, pitch, idx, f);
+        else pull_node<FT>(d, fin, rin, xw, yw, pery, f);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            rho += f[i];
+            jx += kEX[i] * f[i];
+            jy += kEY[i] * f[i];
+        }
+        psi = eos_psi(d, rho, Tt[toff + idx], bad);
+    }
+    s_psi[(ty + 1) * LW + tx + 1] = psi;
+
+    // ring of psi around the tile
+    if ((int)threadIdx.x < NHALO) {
+        const int h = threadIdx.x;
+        int lx, ly;
+        if (h < LW) { lx = h; ly = 0; }
+        else if (h < 2 * LW) { lx = h - LW; ly = LH - 1; }
+        else if (h < 2 * LW + BY) { lx = 0; ly = h - 2 * LW + 1; }
+        else { lx = LW - 1; ly = h - 2 * LW - BY + 1; }
+        int xh = te.x0 + lx - 1, yh = te.y0 + ly - 1;
+        bool ok = true;
+        if (!INNER) {
+            xh = wrap_once(xh, d.nx);
+            ok = xh >= 0 && xh < d.nx;
+            if (pery) yh = wrap_once(yh, d.nyf);
+            ok = ok && yh >= 0 && yh < d.nyf;
+        }
+        double ph = 0.0;
+        if (ok) {
+            double fh[9], rh = 0.0;
+            const uint32_t hidx = (uint32_t)yh * pitch + (uint32_t)xh;
+            if (INNER) pull_inner<FT>(fin, rin, plane, pitch, hidx, fh);
+            else pull_node<FT>(d, fin, rin, xh, yh, pery, fh);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) rh += fh[i];
+            bool dummy = false;  // errors are flagged by the owning tile
+            ph = eos_psi(d, rh, Tt[toff + hidx], dummy);
+        }
+        s_psi[ly * LW + lx] = ph;
+    }
+    __syncthreads();
+
+    if (own) {
+        // Eq. 11 over fluid neighbours, Eq. 14 over wall neighbours
+        double sfx = 0.0, sfy = 0.0, sax = 0.0, say = 0.0;
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const int yn = yr + kEY[i];
+            const bool wall = !INNER && !pery && (yn < 0 || yn >= d.nyf);
+            if (!wall) {
+                const double pn = s_psi[(ty + 1 + kEY[i]) * LW + tx + 1 + kEX[i]];
+                sfx += kWF[i] * kEX[i] * pn;
+                sfy += kWF[i] * kEY[i] * pn;
+            } else {
+                const int xn = wrap_once(xr + kEX[i], d.nx);
+                const double gam = (yn < 0) ? d.gbot[xn] : d.gtop[xn];
+                sax += kWF[i] * kEX[i] * gam;
+                say += kWF[i] * kEY[i] * gam;
+            }
+        }
+        const double Fmx = -d.G * psi * sfx, Fmy = -d.G * psi * sfy;
+        const double Fax = -psi * sax, Fay = -psi * say;
+        const double Fx = Fmx + Fax;
+        const double Fy = Fmy + Fay - (rho - d.rho_bar) * d.g;       // Eq. 15
+        const double inv_rho = frcp(rho);
+        double vx = (jx + 0.5 * Fx) * inv_rho;                         // Eq. 10
+        double vy = (jy + 0.5 * Fy) * inv_rho;
+        if (frozen) { vx = 0.0; vy = 0.0; }
+        const uint32_t oidx = (uint32_t)yr * pitch + (uint32_t)xr;
+
+        if constexpr (MODE == PB_MODE_READ) {
+            double PB_GAS *rdf = gcast_w<double>(d.rd_f);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) (rdf + (uint32_t)i * plane)[oidx] = f[i];
+            gcast_w<double>(d.rd_rho)[oidx] = rho;
+            gcast_w<double>(d.rd_vx)[oidx] = vx;
+            gcast_w<double>(d.rd_vy)[oidx] = vy;
+        } else {
+            // moments m = M f (Eq. 6)
+            const double sa = f[1] + f[2] + f[3] + f[4];
+            const double sd = f[5] + f[6] + f[7] + f[8];
+            const double m1 = -4.0 * f[0] - sa + 2.0 * sd;
+            const double m2 = 4.0 * f[0] - 2.0 * sa + sd;
+            const double m4 = -2.0 * f[1] + 2.0 * f[3] + f[5] - f[6] - f[7] + f[8];
+            const double m6 = -2.0 * f[2] + 2.0 * f[4] + f[5] + f[6] - f[7] - f[8];
+            const double m7 = f[1] - f[2] + f[3] - f[4];
+            const double m8 = f[5] - f[6] + f[7] - f[8];
+            // equilibria (Eq. 6) with u = v of Eq. 10
+            const double u2 = vx * vx + vy * vy;
+            const double meq1 = rho * (-2.0 + 3.0 * u2), meq2 = rho * (1.0 - 3.0 * u2);
+            const double meq4 = -rho * vx, meq6 = -rho * vy;
+            const double meq7 = rho * (vx * vx - vy * vy), meq8 = rho * vx * vy;
+            // forcing of Eq. 9; the varpi term times (1 - s_e/2) equals
+            // 12 varpi s_e |F|^2 / psi^2 because tau_e = 1/s_e
+            const double Fwx = (d.flags & F_FMONLY) ? Fmx : Fmx + Fax;
+            const double Fwy = (d.flags & F_FMONLY) ? Fmy : Fmy + Fay;
+            const double uF = vx * Fx + vy * Fy;
+            const double cw = 12.0 * d.varpi * d.s_e * (Fwx * Fwx + Fwy * Fwy) * frcp(psi * psi);
+            const double cw2 = (d.flags & F_S2PLUS) ? cw : -cw;
+            const double se = d.s_e, sq = d.s_q;
+            const double snu = frcp(d.tau_V + (rho - d.rho_V) * d.ktau);   // Eq. 5
+            const double ms1 = m1 - se * (m1 - meq1) + (1.0 - 0.5 * se) * (6.0 * uF) + cw;
+            const double ms2 = m2 - se * (m2 - meq2) + (1.0 - 0.5 * se) * (-6.0 * uF) + cw2;
+            const double ms3 = jx + Fx;                       // s_j drops out (Eq. 7 + Eq. 10)
+            const double ms4 = m4 - sq * (m4 - meq4) + (1.0 - 0.5 * sq) * (-Fx);
+            const double ms5 = jy + Fy;
+            const double ms6 = m6 - sq * (m6 - meq6) + (1.0 - 0.5 * sq) * (-Fy);
+            const double ms7 = m7 - snu * (m7 - meq7) + (1.0 - 0.5 * snu) * (2.0 * (vx * Fx - vy * Fy));
+            const double ms8 = m8 - snu * (m8 - meq8) + (1.0 - 0.5 * snu) * (vx * Fy + vy * Fx);
+            // f* = M^{-1} m*, M^{-1} = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
+            const double a0 = rho * (1.0 / 9.0), a1 = ms1 * (1.0 / 36.0), a2 = ms2 * (1.0 / 36.0);
+            const double a3 = ms3 * (1.0 / 6.0), a4 = ms4 * (1.0 / 12.0), a5 = ms5 * (1.0 / 6.0);
+            const double a6 = ms6 * (1.0 / 12.0), a7 = ms7 * 0.25, a8 = ms8 * 0.25;
+            const double c0 = a0 - a1 - 2.0 * a2;       // axis-common part
+            const double cd = a0 + 2.0 * a1 + a2;       // diagonal-common part
+            FT PB_GAS *fout = gcast_w<FT>(d.f[pout]);
+            store_pop<FT>(fout, plane, oidx, 0, a0 - 4.0 * a1 + 4.0 * a2, rho);
+            store_pop<FT>(fout, plane, oidx, 1, c0 + a3 - 2.0 * a4 + a7, rho);
+            store_pop<FT>(fout, plane, oidx, 2, c0 + a5 - 2.0 * a6 - a7, rho);
+            store_pop<FT>(fout, plane, oidx, 3, c0 - a3 + 2.0 * a4 + a7, rho);
+            store_pop<FT>(fout, plane, oidx, 4, c0 - a5 + 2.0 * a6 - a7, rho);
+            store_pop<FT>(fout, plane, oidx, 5, cd + a3 + a4 + a5 + a6 + a8, rho);
+            store_pop<FT>(fout, plane, oidx, 6, cd - a3 - a4 + a5 + a6 - a8, rho);
+            store_pop<FT>(fout, plane, oidx, 7, cd - a3 - a4 - a5 - a6 + a8, rho);
+            store_pop<FT>(fout, plane, oidx, 8, cd + a3 + a4 - a5 - a6 - a8, rho);
+            gcast_w<double>(d.rho[pout])[oidx] = rho;
+            gcast_w<double>(d.vx)[oidx] = vx;
+            gcast_w<double>(d.vy)[oidx] = vy;
+        }
+        if (bad || !(rho == rho) || !(vx - vx == 0.0) || !(vy - vy == 0.0)) *s_bad = 1;
+    }
+}
+
 template <typename FT, int BX, int BY, int MODE>
 __global__ __launch_bounds__(BX *BY) void k_flow(const PbDesc *const *__restrict__ dps,
                                                   const PbTile *__restrict__ tiles, int ntiles, int k) {
     constexpr int LW = BX + 2, LH = BY + 2;
-    constexpr int NHALO = 2 * LW + 2 * BY;
-    static_assert(NHALO <= BX * BY, "halo larger than block");
+    static_assert(2 * LW + 2 * BY <= BX * BY, "halo larger than block");
     __shared__ double s_psi[LW * LH];
     __shared__ int s_bad;
-
-    const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
     for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
         const PbTile te = tiles[tl];
-        const PbDesc &d = *dps[te.dom];
-        const bool pery = (d.flags & F_PERY) != 0;
-        const bool frozen = (d.flags & F_FROZEN) != 0;
-        const int pin = (int)((d.par0 + k) & 1), pout = pin ^ 1;
-        const FT *__restrict__ fin = (const FT *)d.f[pin];
-        const double *__restrict__ rin = d.rho[pin];
-        const double *__restrict__ Tt = d.T[pin];
+        cdesc &d = *(const PbDesc PB_CAS *)dps[te.dom];
         if (threadIdx.x == 0) s_bad = 0;
-        bool bad = false;
-
-        // interior node of this thread (positions past the edge wrap once so
-        // that the first column/row beyond holds the periodic neighbour)
-        const int xr = te.x0 + tx, yr = te.y0 + ty;
-        const bool own = xr < d.nx && yr < d.nyf;
-        const int xw = xr - (xr >= d.nx ? d.nx : 0);
-        const int yw = pery ? yr - (yr >= d.nyf ? d.nyf : 0) : yr;
-        const bool live = xw < d.nx && yw < d.nyf;
-        double f[9], rho = 0.0, jx = 0.0, jy = 0.0, psi = 0.0;
-        if (live) {
-            pull_node<FT>(d, fin, rin, xw, yw, pery, f);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                rho += f[i];
-                jx += kEX[i] * f[i];
-                jy += kEY[i] * f[i];
-            }
-            psi = eos_psi(d, rho, Tt[(size_t)(d.nys + yw) * d.pitch + xw], bad);
-        }
-        s_psi[(ty + 1) * LW + tx + 1] = psi;
-
-        // halo ring of psi
-        if ((int)threadIdx.x < NHALO) {
-            int h = threadIdx.x, lx, ly;
-            if (h < LW) { lx = h; ly = 0; }
-            else if (h < 2 * LW) { lx = h - LW; ly = LH - 1; }
-            else if (h < 2 * LW + BY) { lx = 0; ly = h - 2 * LW + 1; }
-            else { lx = LW - 1; ly = h - 2 * LW - BY + 1; }
-            int xh = te.x0 + lx - 1, yh = te.y0 + ly - 1;
-            xh = wrap_once(xh, d.nx);
-            bool ok = xh >= 0 && xh < d.nx;
-            if (pery) yh = wrap_once(yh, d.nyf);
-            ok = ok && yh >= 0 && yh < d.nyf;
-            double ph = 0.0;
-            if (ok) {
-                double fh[9], rh = 0.0;
-                pull_node<FT>(d, fin, rin, xh, yh, pery, fh);
-#pragma unroll
-                for (int i = 0; i < 9; ++i) rh += fh[i];
-                bool dummy = false;  // errors are flagged by the owning tile
-                ph = eos_psi(d, rh, Tt[(size_t)(d.nys + yh) * d.pitch + xh], dummy);
-            }
-            s_psi[ly * LW + lx] = ph;
-        }
-        __syncthreads();
-
-        if (own) {
-            // Eq. 11 over fluid neighbours, Eq. 14 over wall neighbours
-            double sfx = 0.0, sfy = 0.0, sax = 0.0, say = 0.0;
-#pragma unroll
-            for (int i = 1; i < 9; ++i) {
-                const int yn = yr + kEY[i];
-                const bool wall = !pery && (yn < 0 || yn >= d.nyf);
-                if (!wall) {
-                    const double pn = s_psi[(ty + 1 + kEY[i]) * LW + tx + 1 + kEX[i]];
-                    sfx += kWF[i] * kEX[i] * pn;
-                    sfy += kWF[i] * kEY[i] * pn;
-                } else {
-                    const int xn = wrap_once(xr + kEX[i], d.nx);
-                    const double gam = (yn < 0) ? d.gbot[xn] : d.gtop[xn];
-                    sax += kWF[i] * kEX[i] * gam;
-                    say += kWF[i] * kEY[i] * gam;
-                }
-            }
-            const double Fmx = -d.G * psi * sfx, Fmy = -d.G * psi * sfy;
-            const double Fax = -psi * sax, Fay = -psi * say;
-            const double Fx = Fmx + Fax;
-            const double Fy = Fmy + Fay - (rho - d.rho_bar) * d.g;       // Eq. 15
-            const double inv_rho = 1.0 / rho;
-            double vx = (jx + 0.5 * Fx) * inv_rho;                         // Eq. 10
-            double vy = (jy + 0.5 * Fy) * inv_rho;
-            if (frozen) { vx = 0.0; vy = 0.0; }
-            const size_t plane = (size_t)d.nyf * d.pitch;
-            const size_t idx = (size_t)yr * d.pitch + xr;
-
-            if constexpr (MODE == PB_MODE_READ) {
-#pragma unroll
-                for (int i = 0; i < 9; ++i) d.rd_f[(size_t)i * plane + idx] = f[i];
-                d.rd_rho[idx] = rho;
-                d.rd_vx[idx] = vx;
-                d.rd_vy[idx] = vy;
-            } else {
-                // moments m = M f (Eq. 6)
-                const double sa = f[1] + f[2] + f[3] + f[4];
-                const double sd = f[5] + f[6] + f[7] + f[8];
-                const double m1 = -4.0 * f[0] - sa + 2.0 * sd;
-                const double m2 = 4.0 * f[0] - 2.0 * sa + sd;
-                const double m4 = -2.0 * f[1] + 2.0 * f[3] + f[5] - f[6] - f[7] + f[8];
-                const double m6 = -2.0 * f[2] + 2.0 * f[4] + f[5] + f[6] - f[7] - f[8];
-                const double m7 = f[1] - f[2] + f[3] - f[4];
-                const double m8 = f[5] - f[6] + f[7] - f[8];
-                // equilibria (Eq. 6) with u = v of Eq. 10
-                const double u2 = vx * vx + vy * vy;
-                const double meq1 = rho * (-2.0 + 3.0 * u2), meq2 = rho * (1.0 - 3.0 * u2);
-                const double meq4 = -rho * vx, meq6 = -rho * vy;
-                const double meq7 = rho * (vx * vx - vy * vy), meq8 = rho * vx * vy;
-                // forcing of Eq. 9; the varpi term times (1 - s_e/2) equals
-                // 12 varpi s_e |F|^2 / psi^2 because tau_e = 1/s_e
-                const double Fwx = (d.flags & F_FMONLY) ? Fmx : Fmx + Fax;
-                const double Fwy = (d.flags & F_FMONLY) ? Fmy : Fmy + Fay;
-                const double uF = vx * Fx + vy * Fy;
-                const double cw = 12.0 * d.varpi * d.s_e * (Fwx * Fwx + Fwy * Fwy) / (psi * psi);
-                const double cw2 = (d.flags & F_S2PLUS) ? cw : -cw;
-                const double se = d.s_e, sq = d.s_q;
-                const double snu = 1.0 / (d.tau_V + (rho - d.rho_V) * d.ktau);   // Eq. 5
-                const double ms1 = m1 - se * (m1 - meq1) + (1.0 - 0.5 * se) * (6.0 * uF) + cw;
-                const double ms2 = m2 - se * (m2 - meq2) + (1.0 - 0.5 * se) * (-6.0 * uF) + cw2;
-                const double ms3 = jx + Fx;                       // s_j drops out (Eq. 7 + Eq. 10)
-                const double ms4 = m4 - sq * (m4 - meq4) + (1.0 - 0.5 * sq) * (-Fx);
-                const double ms5 = jy + Fy;
-                const double ms6 = m6 - sq * (m6 - meq6) + (1.0 - 0.5 * sq) * (-Fy);
-                const double ms7 = m7 - snu * (m7 - meq7) + (1.0 - 0.5 * snu) * (2.0 * (vx * Fx - vy * Fy));
-                const double ms8 = m8 - snu * (m8 - meq8) + (1.0 - 0.5 * snu) * (vx * Fy + vy * Fx);
-                // f* = M^{-1} m*, M^{-1} = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
-                const double a0 = rho * (1.0 / 9.0), a1 = ms1 * (1.0 / 36.0), a2 = ms2 * (1.0 / 36.0);
-                const double a3 = ms3 * (1.0 / 6.0), a4 = ms4 * (1.0 / 12.0), a5 = ms5 * (1.0 / 6.0);
-                const double a6 = ms6 * (1.0 / 12.0), a7 = ms7 * 0.25, a8 = ms8 * 0.25;
-                const double c0 = a0 - a1 - 2.0 * a2;       // axis-common part
-                const double cd = a0 + 2.0 * a1 + a2;       // diagonal-common part
-                FT *__restrict__ fout = (FT *)d.f[pout];
-                store_pop<FT>(fout, plane, idx, 0, a0 - 4.0 * a1 + 4.0 * a2, rho);
-                store_pop<FT>(fout, plane, idx, 1, c0 + a3 - 2.0 * a4 + a7, rho);
-                store_pop<FT>(fout, plane, idx, 2, c0 + a5 - 2.0 * a6 - a7, rho);
-                store_pop<FT>(fout, plane, idx, 3, c0 - a3 + 2.0 * a4 + a7, rho);
-                store_pop<FT>(fout, plane, idx, 4, c0 - a5 + 2.0 * a6 - a7, rho);
-                store_pop<FT>(fout, plane, idx, 5, cd + a3 + a4 + a5 + a6 + a8, rho);
-                store_pop<FT>(fout, plane, idx, 6, cd - a3 - a4 + a5 + a6 - a8, rho);
-                store_pop<FT>(fout, plane, idx, 7, cd - a3 - a4 - a5 - a6 + a8, rho);
-                store_pop<FT>(fout, plane, idx, 8, cd + a3 + a4 - a5 - a6 - a8, rho);
-                d.rho[pout][idx] = rho;
-                d.vx[idx] = vx;
-                d.vy[idx] = vy;
-            }
-            if (bad || !(rho == rho) || !(vx - vx == 0.0) || !(vy - vy == 0.0)) s_bad = 1;
-        }
+        const bool inner = !(d.flags & F_PERY) && te.x0 >= 2 && te.x0 + BX + 2 <= d.nx && te.y0 >= 2 &&
+                           te.y0 + BY + 2 <= d.nyf;
+        if (inner) flow_tile<FT, BX, BY, MODE, true>(d, te, k, s_psi, &s_bad);
+        else flow_tile<FT, BX, BY, MODE, false>(d, te, k, s_psi, &s_bad);
         __syncthreads();
         if (threadIdx.x == 0 && s_bad) flag_error(d);
+        __syncthreads();
     }
 }
 
-// ------------------------------------------------------------- energy step
-// Thermal node kinds in the LDS tile.
-enum : unsigned char { KIND_NONE = 0, KIND_FIXED = 1, KIND_SOLID = 2, KIND_FLUID = 3 };
+// Thermal node kinds.
+enum : int { KIND_NONE = 0, KIND_FIXED = 1, KIND_SOLID = 2, KIND_FLUID = 3 };
 
-template <int BX, int BY>
-__global__ __launch_bounds__(256) void k_thermal(const PbDesc *const *__restrict__ dps,
-                                                  const PbTile *__restrict__ tiles, int ntiles, int k) {
-    constexpr int H = 4;                        // one ring per RK4 stage
-    constexpr int RW = BX + 2 * H, RH = BY + 2 * H, RN = RW * RH;
-    constexpr int NT = 256;
-    __shared__ double sT0[RN];                  // T(t) (and fixed values)
-    __shared__ double sA[RN], sB[RN];           // stage values (sB holds lambda during set-up)
-    __shared__ double sLE[RN], sLN[RN], sLNE[RN], sLNW[RN];   // link conductances owned by a node
-    __shared__ double sC1[RN], sAL[RN], sBE[RN], sVX[RN], sVY[RN];
-    __shared__ double sAcc[BX * BY];
-    __shared__ unsigned char sKind[RN];
-    __shared__ int s_bad;
+// ----------------------------------------------------- energy step (sweep)
+// Column-sweep form of the same RK4 update.  One wavefront owns 64
+// consecutive columns (56 are written; four on each side are halo) and walks
+// up a strip of H thermal rows plus four halo rows below and above.  At the
+// row n it has just loaded it builds the operator of row n-1 and runs stage 1
+// there, stage 2 on row n-2, stage 3 on row n-3 and stage 4 (the update) on
+// row n-4, so every intermediate lives in registers; x-neighbours come from
+// the adjacent lanes.  The operator of Eq. 24 at a node is folded once per step
+// into  K(T) = sum_i k_i T(x + e_i) + beta sqrt(T(x))  (i = 0..8): diffusion
+// (conservative Eq. 28 with harmonic-mean links), advection (Eq. 27 on T) and
+// the latent term, whose (dP/dT)_rho part A(rho) + B(rho) g(T) gives
+// T (A + B g(T)) = (A - B kappa/Tc) T + B (1 + kappa)/sqrt(Tc) sqrt(T).
+struct Coef9 {
+    double k0, k1, k2, k3, k4, k5, k6, k7, k8, beta;
+};
 
+__device__ __forceinline__ double from_left(double v) { return __shfl_up(v, 1); }    // value at x-1
+__device__ __forceinline__ double from_right(double v) { return __shfl_down(v, 1); } // value at x+1
+
+// harmonic-mean link conductance; a negative value marks the T_top row, whose
+// links take the conductance of the other node
+__device__ __forceinline__ double hlink(double a, double b) {
+    if (a < 0.0) return b;
+    if (b < 0.0) return a;
+    const double s = a + b;
+    return s > 0.0 ? 2.0 * a * b * frcp(s) : 0.0;
+}
+
+struct RowIn {
+    int kind;
+    double T0, lam, rho, vx, vy;
+};
+
+__device__ __forceinline__ RowIn load_row(cdesc &d, const double PB_GAS *Tin, const double PB_GAS *rho,
+                                          const double PB_GAS *vxg, const double PB_GAS *vyg, int n, int xg, bool pery) {
+    RowIn r{KIND_NONE, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int rr = n;
+    if (pery) {
+        rr %= d.nr;
+        if (rr < 0) rr += d.nr;
+    }
+    if (rr >= 0 && rr < d.nr) {
+        r.T0 = Tin[(uint32_t)rr * (uint32_t)d.pitch + (uint32_t)xg];
+        if (rr < d.nys) {
+            r.lam = d.lambda_S;
+            r.kind = (rr == 0 && !pery) ? KIND_FIXED : KIND_SOLID;
+        } else {
+            const uint32_t fi = (uint32_t)(rr - d.nys) * (uint32_t)d.pitch + (uint32_t)xg;
+            r.rho = rho[fi];
+            r.lam = d.Cvchi * r.rho;
+            r.vx = vxg[fi];
+            r.vy = vyg[fi];
+            r.kind = KIND_FLUID;
+        }
+    } else if (!pery && rr == d.nr) {
+        r.T0 = d.T_top;
+        r.lam = -1.0;
+        r.kind = KIND_FIXED;
+    }
+    return r;
+}
+
+__device__ __forceinline__ double apply9(const Coef9 &c, int kind, double Sc, double SR, double SL, double Nc,
+                                         double NR, double NL, double Sc_, double SR_, double SL_) {
+    // rows: S* centre row, N* row above, *_ row below; order of Eq. 2
+    double K = c.k0 * Sc + c.k1 * SR + c.k2 * Nc + c.k3 * SL + c.k4 * Sc_ + c.k5 * NR + c.k6 * NL + c.k7 * SL_ +
+               c.k8 * SR_;
+    if (kind == KIND_FLUID) K += c.beta * fsqrt(Sc);
+    return K;
+}
+
+template <int H>
+__global__ __launch_bounds__(64, 2) void k_thermal_sweep(const PbDesc *const *__restrict__ dps,
+                                                       const PbTile *__restrict__ tiles, int ntiles, int k) {
+    const int lane = threadIdx.x;
     for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
         const PbTile te = tiles[tl];
-        const PbDesc &d = *dps[te.dom];
+        cdesc &d = *(const PbDesc PB_CAS *)dps[te.dom];
         const bool pery = (d.flags & F_PERY) != 0;
         const int pin = (int)((d.par0 + k) & 1), pout = pin ^ 1;
-        const int64_t t = d.t0 + k;
-        const double *__restrict__ Tin = d.T[pin];
-        const double *__restrict__ rho = d.rho[pout];   // rho(t) written by this step's flow
-        const double *__restrict__ vxg = d.vx;
-        const double *__restrict__ vyg = d.vy;
-        if (threadIdx.x == 0) s_bad = 0;
+        const int64_t t1 = d.t0 + k + 1;
+        const double PB_GAS *Tin = gcast<double>(d.T[pin]);
+        double PB_GAS *Tout = gcast_w<double>(d.T[pout]);
+        const double PB_GAS *rhog = gcast<double>(d.rho[pout]);   // rho(t) written by this step's flow
+        const double PB_GAS *vxg = gcast<double>(d.vx);
+        const double PB_GAS *vyg = gcast<double>(d.vy);
+        int xg = (te.x0 - 4 + lane) % d.nx;
+        if (xg < 0) xg += d.nx;
+        const bool out_lane = lane >= 4 && lane < 60 && (te.x0 + lane - 4) < d.nx;
+        const double c1_solid = 1.0 / (d.rho_S * d.C_S);
+        const double lat_a = d.kappa / d.Tc, lat_b = (1.0 + d.kappa) * d.inv_sqrtTc;
+        const double W1 = 6.0 / 9.0, W2 = 6.0 / 36.0, A1 = 3.0 / 9.0, A2 = 3.0 / 36.0;
 
-        // (1) load T(t), lambda, v over the tile plus four rings
-        for (int n = threadIdx.x; n < RN; n += NT) {
-            const int lx = n % RW, ly = n / RW;
-            int xg = te.x0 - H + lx;
-            xg %= d.nx;
-            if (xg < 0) xg += d.nx;
-            int rg = te.y0 - H + ly;
-            unsigned char kind = KIND_NONE;
-            double T0 = 0.0, lam = 0.0, vx = 0.0, vy = 0.0, c1 = 0.0, rh = 0.0;
-            if (pery) {
-                rg %= d.nr;
-                if (rg < 0) rg += d.nr;
+        // carried state; "_1" = row n-1, "_2" = row n-2 and so on
+        int kind_1 = KIND_NONE;
+        double lam_1 = 0.0, lamR_1 = 0.0, rho_1 = 0.0;
+        double vx_1 = 0.0, vy_1 = 0.0, vxL_1 = 0.0, vxR_1 = 0.0, vyL_1 = 0.0, vyR_1 = 0.0;
+        double vxL_2 = 0.0, vxR_2 = 0.0, vyL_2 = 0.0, vyR_2 = 0.0, vy_2 = 0.0;
+        double lN_2 = 0.0, lNEL_2 = 0.0, lNWR_2 = 0.0;      // links of row n-2 seen from row n-1
+        double T0_1 = 0.0, T0_2 = 0.0, T0_3 = 0.0, T0_4 = 0.0;
+        double T0L_1 = 0.0, T0R_1 = 0.0, T0L_2 = 0.0, T0R_2 = 0.0;
+        double s1_2 = 0.0, s1L_2 = 0.0, s1R_2 = 0.0, s1_3 = 0.0, s1L_3 = 0.0, s1R_3 = 0.0;
+        double s2_3 = 0.0, s2L_3 = 0.0, s2R_3 = 0.0, s2_4 = 0.0, s2L_4 = 0.0, s2R_4 = 0.0;
+        double s3_4 = 0.0, s3L_4 = 0.0, s3R_4 = 0.0, s3_5 = 0.0, s3L_5 = 0.0, s3R_5 = 0.0;
+        double acc_2 = 0.0, acc_3 = 0.0, acc_4 = 0.0;
+        Coef9 cf_2{}, cf_3{}, cf_4{};
+        int kd_2 = KIND_NONE, kd_3 = KIND_NONE, kd_4 = KIND_NONE;
+        bool bad = false;
+
+        const int nbeg = te.y0 - 4, nend = te.y0 + H + 3;
+        RowIn nxt = load_row(d, Tin, rhog, vxg, vyg, nbeg, xg, pery);
+#pragma unroll 4
+        for (int j = 0; j < H + 8; ++j) {
+            const int n = nbeg + j;
+            const RowIn cur = nxt;
+            if (n < nend) nxt = load_row(d, Tin, rhog, vxg, vyg, n + 1, xg, pery);
+
+            // new row n: neighbours across lanes
+            const double lamL = from_left(cur.lam), lamR = from_right(cur.lam);
+            const double vxL = from_left(cur.vx), vxR = from_right(cur.vx);
+            const double vyL = from_left(cur.vy), vyR = from_right(cur.vy);
+            const double T0L = from_left(cur.T0), T0R = from_right(cur.T0);
+
+            // operator of row a = n-1
+            const double lE = hlink(lam_1, lamR_1), lN = hlink(lam_1, cur.lam);
+            const double lNE = hlink(lam_1, lamR), lNW = hlink(lam_1, lamL);
+            const double lW = from_left(lE);
+            Coef9 cf{};
+            if (kind_1 == KIND_FLUID || kind_1 == KIND_SOLID) {
+                double C1;
+                if (kind_1 == KIND_FLUID) C1 = frcp(rho_1 * d.Cv); else C1 = c1_solid;
+                const double c1 = W1 * C1 * lE, c2 = W1 * C1 * lN, c3 = W1 * C1 * lW, c4 = W1 * C1 * lN_2;
+                const double c5 = W2 * C1 * lNE, c6 = W2 * C1 * lNW, c7 = W2 * C1 * lNEL_2, c8 = W2 * C1 * lNWR_2;
+                cf.k0 = -(((c1 + c2) + (c3 + c4)) + ((c5 + c6) + (c7 + c8)));
+                cf.k1 = c1; cf.k2 = c2; cf.k3 = c3; cf.k4 = c4;
+                cf.k5 = c5; cf.k6 = c6; cf.k7 = c7; cf.k8 = c8;
+                if (kind_1 == KIND_FLUID) {
+                    // Eq. 27 on v (v = 0 outside the fluid)
+                    const double divv = 3.0 * ((1.0 / 9.0) * (vxR_1 - vxL_1 + cur.vy - vy_2) +
+                                               (1.0 / 36.0) * (vxR - vxL - vxL_2 + vxR_2 + vyR + vyL - vyL_2 - vyR_2));
+                    const double br = d.b * rho_1;
+                    const double A = rho_1 * d.R * frcp(1.0 - br);
+                    const double B = d.a * d.kappa * rho_1 * rho_1 * frcp(1.0 + 2.0 * br - br * br);
+                    const double AL = -C1 * divv * A, BE = -C1 * divv * B;
+                    cf.k0 += AL - BE * lat_a;
+                    cf.beta = BE * lat_b;
+                    // advection -v.grad T with Eq. 27
+                    cf.k1 -= A1 * vx_1;  cf.k3 += A1 * vx_1;
+                    cf.k2 -= A1 * vy_1;  cf.k4 += A1 * vy_1;
+                    cf.k5 -= A2 * (vx_1 + vy_1);  cf.k7 += A2 * (vx_1 + vy_1);
+                    cf.k6 -= A2 * (vy_1 - vx_1);  cf.k8 += A2 * (vy_1 - vx_1);
+                }
             }
-            if (rg >= 0 && rg < d.nr) {
-                T0 = Tin[(size_t)rg * d.pitch + xg];
-                if (rg < d.nys) {
-                    lam = d.lambda_S;
-                    kind = (rg == 0 && !pery) ? KIND_FIXED : KIND_SOLID;
-                    c1 = 1.0 / (d.rho_S * d.C_S);
+
+            // stage 1 on row n-1 (input T0 rows n-2, n-1, n)
+            const double K1 = apply9(cf, kind_1, T0_1, T0R_1, T0L_1, cur.T0, T0R, T0L, T0_2, T0R_2, T0L_2);
+            const double s1 = T0_1 + 0.5 * K1;
+            const double acc1 = K1;
+            const double s1L = from_left(s1), s1R = from_right(s1);
+            // stage 2 on row n-2 (input s1 rows n-3, n-2, n-1)
+            const double K2 = apply9(cf_2, kd_2, s1_2, s1R_2, s1L_2, s1, s1R, s1L, s1_3, s1R_3, s1L_3);
+            const double s2 = T0_2 + 0.5 * K2;
+            const double acc2 = acc_2 + 2.0 * K2;
+            const double s2L = from_left(s2), s2R = from_right(s2);
+            // stage 3 on row n-3 (input s2 rows n-4, n-3, n-2)
+            const double K3 = apply9(cf_3, kd_3, s2_3, s2R_3, s2L_3, s2, s2R, s2L, s2_4, s2R_4, s2L_4);
+            const double s3 = T0_3 + K3;
+            const double acc3 = acc_3 + 2.0 * K3;
+            const double s3L = from_left(s3), s3R = from_right(s3);
+            // stage 4 and the update on row e = n-4 (input s3 rows n-5, n-4, n-3)
+            const double K4 = apply9(cf_4, kd_4, s3_4, s3R_4, s3L_4, s3, s3R, s3L, s3_5, s3R_5, s3L_5);
+            const int e = n - 4;
+            if (out_lane && e >= te.y0 && e < te.y0 + H && e >= 0 && e < d.nr) {
+                double Tn;
+                if (kd_4 == KIND_FIXED) {
+                    Tn = (t1 >= d.alt_t0 && t1 < d.alt_t1) ? gcast<double>(d.Tb_alt)[xg]
+                                                           : gcast<double>(d.Tb)[xg];   // T_b(x, t+1)
                 } else {
-                    const size_t fi = (size_t)(rg - d.nys) * d.pitch + xg;
-                    rh = rho[fi];
-                    lam = d.Cvchi * rh;
-                    vx = vxg[fi];
-                    vy = vyg[fi];
-                    kind = KIND_FLUID;
-                    c1 = 1.0 / (rh * d.Cv);
+                    Tn = T0_4 + (1.0 / 6.0) * (acc_4 + K4);
                 }
-            } else if (!pery && rg == d.nr) {           // virtual row at T_top
-                T0 = d.T_top;
-                lam = -1.0;                              // marker: link takes the other side
-                kind = KIND_FIXED;
+                Tout[(uint32_t)e * (uint32_t)d.pitch + (uint32_t)xg] = Tn;
+                bad = bad || !(Tn - Tn == 0.0);
             }
-            sT0[n] = T0;
-            sB[n] = lam;
-            sVX[n] = vx;
-            sVY[n] = vy;
-            sC1[n] = c1;
-            sAL[n] = rh;
-            sKind[n] = kind;
-        }
-        __syncthreads();
 
-        // (2) link conductances (harmonic mean, flux-continuous at the heater
-        //     top) and the per-node latent-heat coefficients
-        for (int n = threadIdx.x; n < RN; n += NT) {
-            const int lx = n % RW, ly = n / RW;
-            const double la = sB[n];
-            auto link = [&](int m) -> double {
-                const double lb = sB[m];
-                if (la < 0.0) return lb;
-                if (lb < 0.0) return la;
-                const double s = la + lb;
-                return s > 0.0 ? 2.0 * la * lb / s : 0.0;
-            };
-            sLE[n] = (lx + 1 < RW) ? link(n + 1) : 0.0;
-            sLN[n] = (ly + 1 < RH) ? link(n + RW) : 0.0;
-            sLNE[n] = (lx + 1 < RW && ly + 1 < RH) ? link(n + RW + 1) : 0.0;
-            sLNW[n] = (lx >= 1 && ly + 1 < RH) ? link(n + RW - 1) : 0.0;
-            double al = 0.0, be = 0.0;
-            if (sKind[n] == KIND_FLUID && lx >= 1 && lx < RW - 1 && ly >= 1 && ly < RH - 1) {
-                // Eq. 27 on v (v = 0 on solid and virtual nodes)
-                const double divv =
-                    3.0 * ((1.0 / 9.0) * (sVX[n + 1] - sVX[n - 1] + sVY[n + RW] - sVY[n - RW]) +
-                           (1.0 / 36.0) * (sVX[n + RW + 1] - sVX[n + RW - 1] - sVX[n - RW - 1] + sVX[n - RW + 1] +
-                                           sVY[n + RW + 1] + sVY[n + RW - 1] - sVY[n - RW - 1] - sVY[n - RW + 1]));
-                // (dP/dT)_rho = A(rho) + B(rho) g(T), g = (1 + kappa(1 - sqrt(T/Tc))) / sqrt(T Tc)
-                const double rh = sAL[n], br = d.b * rh;
-                const double A = rh * d.R / (1.0 - br);
-                const double B = d.a * rh * rh * d.kappa / (1.0 + 2.0 * br - br * br);
-                const double c = -sC1[n] * divv;
-                al = c * A;
-                be = c * B;
-            }
-            sAL[n] = al;   // only this thread reads or writes sAL[n], sBE[n] in this pass
-            sBE[n] = be;
+            // shift the windows by one row
+            s3_5 = s3_4; s3L_5 = s3L_4; s3R_5 = s3R_4;
+            s3_4 = s3; s3L_4 = s3L; s3R_4 = s3R;
+            s2_4 = s2_3; s2L_4 = s2L_3; s2R_4 = s2R_3;
+            s2_3 = s2; s2L_3 = s2L; s2R_3 = s2R;
+            s1_3 = s1_2; s1L_3 = s1L_2; s1R_3 = s1R_2;
+            s1_2 = s1; s1L_2 = s1L; s1R_2 = s1R;
+            acc_4 = acc3; acc_3 = acc2; acc_2 = acc1;
+            cf_4 = cf_3; kd_4 = kd_3;
+            cf_3 = cf_2; kd_3 = kd_2;
+            cf_2 = cf; kd_2 = kind_1;
+            T0_4 = T0_3; T0_3 = T0_2;
+            T0_2 = T0_1; T0L_2 = T0L_1; T0R_2 = T0R_1;
+            T0_1 = cur.T0; T0L_1 = T0L; T0R_1 = T0R;
+            lN_2 = lN; lNEL_2 = from_left(lNE); lNWR_2 = from_right(lNW);
+            vxL_2 = vxL_1; vxR_2 = vxR_1; vyL_2 = vyL_1; vyR_2 = vyR_1; vy_2 = vy_1;
+            vx_1 = cur.vx; vy_1 = cur.vy; vxL_1 = vxL; vxR_1 = vxR; vyL_1 = vyL; vyR_1 = vyR;
+            lam_1 = cur.lam; lamR_1 = lamR; rho_1 = cur.rho; kind_1 = cur.kind;
         }
-        __syncthreads();
-
-        // (3) RK4 stages on shrinking regions: h1 on ring 3, h2 on ring 2,
-        //     h3 on ring 1, h4 on the tile
-#pragma unroll 1
-        for (int st = 1; st <= 4; ++st) {
-            const double *S = (st == 1) ? sT0 : ((st == 3) ? sB : sA);
-            double *O = (st == 2) ? sB : sA;
-            const int m = st;                          // stage st runs on the tile plus (4 - st) rings
-            const int w = RW - 2 * m, h = RH - 2 * m;
-            for (int q = threadIdx.x; q < w * h; q += NT) {
-                const int lx = m + q % w, ly = m + q / w;
-                const int n = ly * RW + lx;
-                const unsigned char kind = sKind[n];
-                const double Tc = S[n];
-                double K = 0.0;
-                if (kind >= KIND_SOLID) {
-                    const double TE = S[n + 1], TW = S[n - 1], TN = S[n + RW], TS = S[n - RW];
-                    const double TNE = S[n + RW + 1], TNW = S[n + RW - 1], TSW = S[n - RW - 1], TSE = S[n - RW + 1];
-                    const double diff =
-                        6.0 * ((1.0 / 9.0) * (sLE[n] * (TE - Tc) + sLN[n] * (TN - Tc) + sLE[n - 1] * (TW - Tc) +
-                                              sLN[n - RW] * (TS - Tc)) +
-                               (1.0 / 36.0) * (sLNE[n] * (TNE - Tc) + sLNW[n] * (TNW - Tc) +
-                                               sLNE[n - RW - 1] * (TSW - Tc) + sLNW[n - RW + 1] * (TSE - Tc)));
-                    K = sC1[n] * diff;
-                    if (kind == KIND_FLUID) {
-                        const double gx = 3.0 * ((1.0 / 9.0) * (TE - TW) + (1.0 / 36.0) * (TNE - TNW - TSW + TSE));
-                        const double gy = 3.0 * ((1.0 / 9.0) * (TN - TS) + (1.0 / 36.0) * (TNE + TNW - TSW - TSE));
-                        const double sq = sqrt(Tc);
-                        const double gT = (1.0 + d.kappa * (1.0 - sq * d.inv_sqrtTc)) / (sq * d.sqrtTc);
-                        K += -(sVX[n] * gx + sVY[n] * gy) + Tc * (sAL[n] + sBE[n] * gT);
-                    }
-                }
-                const double T0 = sT0[n];
-                const bool in_tile = lx >= H && lx < H + BX && ly >= H && ly < H + BY;
-                const int ti = (ly - H) * BX + (lx - H);
-                if (st == 1) {
-                    O[n] = T0 + 0.5 * K;
-                    if (in_tile) sAcc[ti] = K;
-                } else if (st == 2) {
-                    O[n] = T0 + 0.5 * K;
-                    if (in_tile) sAcc[ti] += 2.0 * K;
-                } else if (st == 3) {
-                    O[n] = T0 + K;
-                    if (in_tile) sAcc[ti] += 2.0 * K;
-                } else {
-                    // final update and store of the tile
-                    const int xg = te.x0 + (lx - H), rg = te.y0 + (ly - H);
-                    if (xg < d.nx && rg < d.nr) {
-                        double Tn;
-                        if (kind == KIND_FIXED) {                     // Dirichlet row: T_b(x, t+1)
-                            const int64_t t1 = t + 1;
-                            Tn = (t1 >= d.alt_t0 && t1 < d.alt_t1) ? d.Tb_alt[xg] : d.Tb[xg];
-                        } else {
-                            const double acc = sAcc[ti] + K;
-                            Tn = T0 + (1.0 / 6.0) * acc;
-                        }
-                        d.T[pout][(size_t)rg * d.pitch + xg] = Tn;
-                        if (!(Tn - Tn == 0.0)) s_bad = 1;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0 && s_bad) flag_error(d);
-        __syncthreads();
+        if (bad) flag_error(d);
     }
 }
 
@@ -436,13 +540,13 @@ __global__ __launch_bounds__(256) void k_thermal(const PbDesc *const *__restrict
 // One block per domain; fixed-order tree reduction so the result does not
 // depend on what else runs.
 __global__ __launch_bounds__(256) void k_flux(const PbDesc *const *__restrict__ dps, int k) {
-    const PbDesc &d = *dps[blockIdx.x];
+    cdesc &d = *(const PbDesc PB_CAS *)dps[blockIdx.x];
     const int64_t t = d.t0 + k + 1;
     if ((d.flags & F_PERY) || d.nys < 3 || d.nyf < 1) return;
     if (t < d.fl_ta || t >= d.fl_tb || ((t - d.fl_ta) % d.fl_every) != 0) return;
     const int pout = (int)((d.par0 + k + 1) & 1);
-    const double *T = d.T[pout];
-    const double *rho = d.rho[pout];
+    const double PB_GAS *T = gcast<double>(d.T[pout]);
+    const double PB_GAS *rho = gcast<double>(d.rho[pout]);
     __shared__ double sb[256], st[256], sw[256];
     double ab = 0.0, at = 0.0, aw = 0.0;
     const int r = d.nys - 1;
@@ -477,13 +581,14 @@ __global__ __launch_bounds__(256) void k_flux(const PbDesc *const *__restrict__ 
     if (threadIdx.x == 0) {
         const double inx = 1.0 / (double)d.nx;
         const double qb = sb[0] * inx, qt = st[0] * inx, tw = sw[0] * inx;
-        d.flux[0] = qb;
-        d.flux[1] = qt;
-        d.flux[2] = tw;
-        d.flux[3] += qb;
-        d.flux[4] += qt;
-        d.flux[5] += tw;
-        d.flux[6] += 1.0;
+        double PB_GAS *fl = gcast_w<double>(d.flux);
+        fl[0] = qb;
+        fl[1] = qt;
+        fl[2] = tw;
+        fl[3] += qb;
+        fl[4] += qt;
+        fl[5] += tw;
+        fl[6] += 1.0;
     }
 }
 
@@ -540,7 +645,8 @@ __global__ void k_advance(PbDesc *const *__restrict__ dps, int ndom, int nsteps)
 // ------------------------------------------------------------ launch helpers
 // Flow tile variants: (BX, BY) with BX * BY threads per block.
 static const int kFlowShapes[][2] = {{64, 4}, {64, 8}, {32, 8}, {128, 4}, {32, 16}, {64, 16}};
-static const int kThermalShapes[][2] = {{32, 8}, {64, 4}, {16, 16}, {32, 16}};
+// column sweeps of 56 written columns x H rows
+static const int kThermalShapes[][2] = {{56, 32}, {56, 64}, {56, 16}, {56, 128}};
 
 int pb_flow_variants() { return (int)(sizeof(kFlowShapes) / sizeof(kFlowShapes[0])); }
 int pb_thermal_variants() { return (int)(sizeof(kThermalShapes) / sizeof(kThermalShapes[0])); }
@@ -586,10 +692,10 @@ hipError_t pb_launch_flow(int prec, int mode, int variant, const PbDesc *const *
 hipError_t pb_launch_thermal(int variant, const PbDesc *const *dps, const PbTile *d_tiles, int ntiles, int grid, int k,
                              hipStream_t s) {
     switch (variant) {
-        case 0: hipLaunchKernelGGL((k_thermal<32, 8>), dim3(grid), dim3(256), 0, s, dps, d_tiles, ntiles, k); break;
-        case 1: hipLaunchKernelGGL((k_thermal<64, 4>), dim3(grid), dim3(256), 0, s, dps, d_tiles, ntiles, k); break;
-        case 2: hipLaunchKernelGGL((k_thermal<16, 16>), dim3(grid), dim3(256), 0, s, dps, d_tiles, ntiles, k); break;
-        case 3: hipLaunchKernelGGL((k_thermal<32, 16>), dim3(grid), dim3(256), 0, s, dps, d_tiles, ntiles, k); break;
+        case 0: hipLaunchKernelGGL((k_thermal_sweep<32>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
+        case 1: hipLaunchKernelGGL((k_thermal_sweep<64>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
+        case 2: hipLaunchKernelGGL((k_thermal_sweep<16>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
+        case 3: hipLaunchKernelGGL((k_thermal_sweep<128>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
