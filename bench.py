@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--tile", default="0x0")
     ap.add_argument("--thermal-tile", type=int, default=0)
     ap.add_argument("--no-tune", action="store_true", help="skip the tile autotuner; use --tile/--thermal-tile")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one device-to-device copy of MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -107,6 +109,15 @@ def main():
     tx, ty = (int(v) for v in args.tile.split("x"))
     thermal_tile = args.thermal_tile
     torch.cuda.set_device(0)
+    if args.copy_calibration > 0:
+        n = args.copy_calibration << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"bench: calibration copy of {n} bytes done", file=sys.stderr, flush=True)
+        del src, dst
     tuned = None
     if not args.no_tune:
         from paper_1911_10747_amd import autotune

@@ -394,14 +394,17 @@ __device__ __forceinline__ RowIn load_row(cdesc &d, const double PB_GAS *Tin, co
 __device__ __forceinline__ double apply9(const Coef9 &c, int kind, double Sc, double SR, double SL, double Nc,
                                          double NR, double NL, double Sc_, double SR_, double SL_) {
     // rows: S* centre row, N* row above, *_ row below; order of Eq. 2
-    double K = c.k0 * Sc + c.k1 * SR + c.k2 * Nc + c.k3 * SL + c.k4 * Sc_ + c.k5 * NR + c.k6 * NL + c.k7 * SL_ +
-               c.k8 * SR_;
+    // three independent row sums keep the dependency chain short
+    const double rm = c.k0 * Sc + c.k1 * SR + c.k3 * SL;
+    const double ra = c.k2 * Nc + c.k5 * NR + c.k6 * NL;
+    const double rb = c.k4 * Sc_ + c.k7 * SL_ + c.k8 * SR_;
+    double K = rm + (ra + rb);
     if (kind == KIND_FLUID) K += c.beta * fsqrt(Sc);
     return K;
 }
 
-template <int H>
-__global__ __launch_bounds__(64, 2) void k_thermal_sweep(const PbDesc *const *__restrict__ dps,
+template <int H, int WPE>
+__global__ __launch_bounds__(64, WPE) void k_thermal_sweep(const PbDesc *const *__restrict__ dps,
                                                        const PbTile *__restrict__ tiles, int ntiles, int k) {
     const int lane = threadIdx.x;
     for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
@@ -646,7 +649,7 @@ __global__ void k_advance(PbDesc *const *__restrict__ dps, int ndom, int nsteps)
 // Flow tile variants: (BX, BY) with BX * BY threads per block.
 static const int kFlowShapes[][2] = {{64, 4}, {64, 8}, {32, 8}, {128, 4}, {32, 16}, {64, 16}};
 // column sweeps of 56 written columns x H rows
-static const int kThermalShapes[][2] = {{56, 32}, {56, 64}, {56, 16}, {56, 128}};
+static const int kThermalShapes[][2] = {{56, 32}, {56, 64}, {56, 16}, {56, 8}};
 
 int pb_flow_variants() { return (int)(sizeof(kFlowShapes) / sizeof(kFlowShapes[0])); }
 int pb_thermal_variants() { return (int)(sizeof(kThermalShapes) / sizeof(kThermalShapes[0])); }
@@ -692,10 +695,10 @@ hipError_t pb_launch_flow(int prec, int mode, int variant, const PbDesc *const *
 hipError_t pb_launch_thermal(int variant, const PbDesc *const *dps, const PbTile *d_tiles, int ntiles, int grid, int k,
                              hipStream_t s) {
     switch (variant) {
-        case 0: hipLaunchKernelGGL((k_thermal_sweep<32>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
-        case 1: hipLaunchKernelGGL((k_thermal_sweep<64>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
-        case 2: hipLaunchKernelGGL((k_thermal_sweep<16>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
-        case 3: hipLaunchKernelGGL((k_thermal_sweep<128>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
+        case 0: hipLaunchKernelGGL((k_thermal_sweep<32, 2>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
+        case 1: hipLaunchKernelGGL((k_thermal_sweep<64, 2>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
+        case 2: hipLaunchKernelGGL((k_thermal_sweep<16, 2>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
+        case 3: hipLaunchKernelGGL((k_thermal_sweep<8, 2>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
