@@ -68,11 +68,13 @@ def cpu_baseline(nx, nyf, nys, steps):
     Ts = W.T_SAT_OVER_TC * Tc
     rl, rv, _ = eos.maxwell(Ts, P["a"], P["b"], P["R"], P["omega"], Tc)
     import numpy as np
-    P.update(nx=nx, nyf=nyf, nys=nys, Tc=Tc, rho_L=rl, rho_V=rv, rho_S=W.RHO_S_OVER_RHO_L * rl)
+    P.update(nx=nx, nyf=nyf, nys=nys, Tc=Tc, rho_L=rl, rho_V=rv, rho_S=W.RHO_S_OVER_RHO_L * rl,
+             g=W.gravity_for_height(nyf))
     dom = orc.Domain(**P)
     Tb = W.spot_Tb(nx, Ts + 0.1 * Tc, max(1, nx // 64), 0)
     gam = np.full(nx, -0.7 * eos.psi(rl, Ts, P["a"], P["b"], P["R"], P["omega"], Tc))
-    dom.set_bc(Ts, Tb, gamma_bot=gam, gamma_top=gam)
+    gtop = np.full(nx, -eos.psi(rv, Ts, P["a"], P["b"], P["R"], P["omega"], Tc))
+    dom.set_bc(Ts, Tb, gamma_bot=gam, gamma_top=gtop)
     dom.set_fields(W.layered_rho(nx, nyf, int(round(0.4 * nyf)), rl, rv), W.thermal_init(nx, nys, nyf, Ts, Tb))
     t0 = time.perf_counter()
     dom.step(steps)
@@ -80,6 +82,57 @@ def cpu_baseline(nx, nyf, nys, steps):
     return dict(value=nx * nyf * steps / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
                 sample=f"{steps} steps of the full {nx}x{nyf}+{nys} domain, serial FP64 C oracle, one core, "
                        f"{dt:.1f} s")
+
+
+def _serve_jobs(jobs, precision, batching, max_slots, mem_budget, realtime, time_scale=1.0):
+    from paper_1911_10747_amd import presets, serve
+    srv = serve.Server(mem_budget=mem_budget, max_slots=max_slots, precision=precision, chunk_steps=2000,
+                       graph_steps=100 if batching else 0, batching=batching)
+    if realtime:
+        res, wall = serve.run_trace(srv, jobs, time_scale=time_scale, max_wall_s=900)
+    else:
+        t0 = time.perf_counter()
+        ids = [srv.submit(presets.JobSpec(nx=j["nx"], nyf=j["nyf"], nys=j["nys"], superheat=j["superheat"],
+                                          steps=j["steps"], seed=j["seed"]), arrival=t0) for j in jobs]
+        srv.drain(max_wall_s=900)
+        wall = time.perf_counter() - t0
+        res = [srv.result(i) for i in ids]
+    lat = serve.latency_stats(res)
+    return dict(jobs=len(res), wall_s=round(wall, 3), jobs_per_hour=round(len(res) / wall * 3600.0, 1),
+                p50_latency_s=round(lat["p50_s"], 4), p99_latency_s=round(lat["p99_s"], 4),
+                mlups=round(srv.stats.node_updates / wall / 1e6, 1), max_resident=srv.stats.max_resident,
+                chunks=srv.stats.chunks, errors=sum(1 for r in res if r.error)), [r.q_mean for r in res]
+
+
+def serving_legs(log):
+    """Boiling-curve jobs: (1) 32 jobs of log-uniform size 128..1024 x 128..512
+    (heater 1/20 of the height), superheat U[0.02, 0.30] Tc, 20000 steps, all
+    submitted at once; (2) a Poisson stream of 48 jobs, sizes 64..2048 x
+    64..1024, 5000-20000 steps, arrival rate 4 jobs/s.  FP32-deviation
+    continuous batching against FP64 one job at a time, same jobs."""
+    import numpy as np
+    import workloads as W
+    out = {}
+    curve = W.batch_jobs(seed=0, n=32, steps=20000)
+    log("serving: boiling curve, 32 jobs, FP32 batched")
+    b32, q32 = _serve_jobs(curve, 1, True, 64, 32 << 30, realtime=False)
+    log("serving: boiling curve, 32 jobs, FP64 one at a time")
+    b64, q64 = _serve_jobs(curve, 0, False, 1, 32 << 30, realtime=False)
+    dq = np.abs(np.array(q32) - np.array(q64)) / np.maximum(np.abs(np.array(q64)), 1e-30)
+    out["boiling_curve"] = dict(fp32_batched=b32, fp64_one_at_a_time=b64,
+                                speedup_jobs_per_hour=round(b32["jobs_per_hour"] / b64["jobs_per_hour"], 2),
+                                heat_flux_rel_diff_median=float(np.median(dq)), heat_flux_rel_diff_max=float(dq.max()),
+                                within_3pct=int((dq <= 0.03).sum()))
+    stream = W.job_stream(seed=0, n=48, rate_per_s=4.0)
+    log("serving: Poisson stream, 48 jobs, FP32 continuous batching")
+    s32, q32 = _serve_jobs(stream, 1, True, 32, 4 << 30, realtime=True)
+    log("serving: Poisson stream, 48 jobs, FP64 one at a time")
+    s64, q64 = _serve_jobs(stream, 0, False, 1, 4 << 30, realtime=True)
+    dq = np.abs(np.array(q32) - np.array(q64)) / np.maximum(np.abs(np.array(q64)), 1e-30)
+    out["poisson_stream"] = dict(rate_jobs_per_s=4.0, fp32_batched=s32, fp64_one_at_a_time=s64,
+                                 heat_flux_rel_diff_median=float(np.median(dq)),
+                                 heat_flux_rel_diff_max=float(dq.max()), within_3pct=int((dq <= 0.03).sum()))
+    return out
 
 
 def main():
@@ -93,6 +146,7 @@ def main():
     ap.add_argument("--tile", default="0x0")
     ap.add_argument("--thermal-tile", type=int, default=0)
     ap.add_argument("--no-tune", action="store_true", help="skip the tile autotuner; use --tile/--thermal-tile")
+    ap.add_argument("--no-serving", action="store_true", help="skip the boiling-curve / job-stream legs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -176,6 +230,8 @@ def main():
         },
     }
     dom.close()
+    if not args.no_serving:
+        out["serving"] = serving_legs(lambda m: print("bench: " + m, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         print(f"bench: oracle on {args.cpu_steps} steps", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(nx, nyf, nys, args.cpu_steps)

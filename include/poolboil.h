@@ -183,6 +183,12 @@ int pb_eos_critical_temperature(double a, double b, double R, double *Tc);
 int pb_eos_coexistence(double a, double b, double R, double omega, double Tc, double T, double *rho_L,
                        double *rho_V);
 
+/* Latent heat h_fg at T < Tc for Eq. 13 by the Clausius-Clapeyron relation
+ * h_fg = T (1/rho_V - 1/rho_L) dP_sat/dT, with dP_sat/dT from centred
+ * differences of the Maxwell saturation pressure (Section 3.1, Eq. 37 uses it
+ * for the Jakob number). */
+int pb_eos_latent_heat(double a, double b, double R, double omega, double Tc, double T, double *h_fg);
+
 /* psi of Eq. 12 (c = 1, c_s^2 = 1/3) with P_EOS of Eq. 13 at (rho, T); used
  * to express wall adhesion gamma = G_w psi(rho_w) of Eq. 14. */
 int pb_eos_psi(double a, double b, double R, double omega, double Tc, double G, double rho, double T, double *psi);

@@ -857,6 +857,25 @@ int pb_eos_coexistence(double a, double b, double R, double omega, double Tc, do
     return PB_OK;
 }
 
+int pb_eos_latent_heat(double a, double b, double R, double omega, double Tc, double T, double *h_fg) {
+    if (!h_fg) return fail(PB_EINVAL, "output is NULL");
+    const double kap = 0.37464 + 1.54226 * omega - 0.26992 * omega * omega;
+    auto psat = [&](double TT, double *rl, double *rv) -> int {
+        return pb_eos_coexistence(a, b, R, omega, Tc, TT, rl, rv);
+    };
+    auto pressure = [&](double TT, double r) {
+        const double s = 1.0 + kap * (1.0 - std::sqrt(TT / Tc));
+        return r * R * TT / (1.0 - b * r) - a * s * s * r * r / (1.0 + 2.0 * b * r - b * b * r * r);
+    };
+    double rl, rv, rl1, rv1, rl2, rv2;
+    const double dT = 1e-5 * Tc;
+    int rc;
+    if ((rc = psat(T, &rl, &rv)) || (rc = psat(T + dT, &rl1, &rv1)) || (rc = psat(T - dT, &rl2, &rv2))) return rc;
+    const double dPdT = (pressure(T + dT, rl1) - pressure(T - dT, rl2)) / (2.0 * dT);
+    *h_fg = T * (1.0 / rv - 1.0 / rl) * dPdT;
+    return PB_OK;
+}
+
 int pb_eos_psi(double a, double b, double R, double omega, double Tc, double G, double rho, double T, double *psi) {
     if (!psi || !(G < 0) || !(rho > 0) || !(T > 0) || !(Tc > 0) || !(rho * b < 1.0))
         return fail(PB_EINVAL, "need psi output, G < 0, 0 < rho < 1/b, T, Tc > 0");

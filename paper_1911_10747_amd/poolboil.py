@@ -22,7 +22,7 @@ EXPORTED = [
     "pb_step", "pb_sync", "pb_read_fields", "pb_flux_window", "pb_heat_flux", "pb_profile_steps", "pb_time",
     "pb_rho_bar",
     "pb_batch_create", "pb_batch_step", "pb_batch_destroy", "pb_eos_critical_temperature", "pb_eos_coexistence",
-    "pb_eos_psi", "pb_last_error", "pb_version",
+    "pb_eos_psi", "pb_eos_latent_heat", "pb_last_error", "pb_version",
 ]
 
 
@@ -92,6 +92,7 @@ def _load():
         "pb_eos_critical_temperature": ([C.c_double, C.c_double, C.c_double, dp], C.c_int),
         "pb_eos_coexistence": ([C.c_double] * 6 + [dp, dp], C.c_int),
         "pb_eos_psi": ([C.c_double] * 8 + [dp], C.c_int),
+        "pb_eos_latent_heat": ([C.c_double] * 6 + [dp], C.c_int),
         "pb_last_error": ([], C.c_char_p),
         "pb_version": ([], C.c_int),
     }
@@ -153,6 +154,12 @@ def coexistence(a, b, R, omega, Tc, T):
 def eos_psi(a, b, R, omega, Tc, G, rho, T):
     out = C.c_double()
     _check(lib.pb_eos_psi(a, b, R, omega, Tc, G, rho, T, C.byref(out)))
+    return out.value
+
+
+def latent_heat(a, b, R, omega, Tc, T):
+    out = C.c_double()
+    _check(lib.pb_eos_latent_heat(a, b, R, omega, Tc, T, C.byref(out)))
     return out.value
 
 
@@ -258,9 +265,9 @@ class Batch:
     """Lock-step stepping of several domains in shared launches."""
 
     def __init__(self, domains, steps_per_graph=0, persistent_blocks=0, stream=None):
+        """stream None: the library steps the batch on a stream of its own,
+        ordered after (and before) the members' own streams."""
         self.domains = list(domains)
-        if stream is None:
-            stream = self.domains[0].stream
         arr = (C.c_void_p * len(self.domains))(*[d.handle for d in self.domains])
         h = C.c_void_p()
         _check(lib.pb_batch_create(arr, len(self.domains), int(steps_per_graph), int(persistent_blocks), stream,

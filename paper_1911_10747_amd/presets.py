@@ -20,6 +20,7 @@ class Derived:
     rho_L: float
     rho_V: float
     psi_L: float
+    psi_V: float
 
 
 def derived(a=None, b=None, R=None, omega=None, G=-1.0, t_ratio=W.T_SAT_OVER_TC):
@@ -31,7 +32,7 @@ def derived(a=None, b=None, R=None, omega=None, G=-1.0, t_ratio=W.T_SAT_OVER_TC)
     Tc = pb.critical_temperature(a, b, R)
     Ts = t_ratio * Tc
     rl, rv = pb.coexistence(a, b, R, omega, Tc, Ts)
-    return Derived(Tc, Ts, rl, rv, pb.eos_psi(a, b, R, omega, Tc, G, rl, Ts))
+    return Derived(Tc, Ts, rl, rv, pb.eos_psi(a, b, R, omega, Tc, G, rl, Ts), pb.eos_psi(a, b, R, omega, Tc, G, rv, Ts))
 
 
 @dataclass
@@ -47,7 +48,7 @@ class JobSpec:
     precision: int = pb.PB_FP32_DEV
     spots_per_columns: int = 64      # one +2% hot spot per this many columns (at least one)
     liquid_fraction: float = 0.4     # liquid below this fraction of the fluid height
-    gamma_frac: float = 0.7          # wall adhesion gamma = -gamma_frac * psi_L
+    gamma_frac: float = 0.7          # heater-wall adhesion gamma = -gamma_frac * psi_L (top wall: -psi_V)
     tile: tuple = (0, 0)
     thermal_tile: int = 0
     flux_every: int = 10
@@ -57,6 +58,7 @@ class JobSpec:
 def make_config(spec, d=None):
     d = derived() if d is None else d
     P = dict(W.BASE_PARAMS)
+    P["g"] = W.gravity_for_height(spec.nyf)
     P.update({k: v for k, v in spec.overrides.items() if k in P})
     return pb.make_config(nx=spec.nx, ny_fluid=spec.nyf, ny_solid=spec.nys, precision=spec.precision, flags=0,
                           tile_x=spec.tile[0], tile_y=spec.tile[1], thermal_tile=spec.thermal_tile,
@@ -70,7 +72,7 @@ def initial_state(spec, d=None):
     n_spots = max(1, spec.nx // spec.spots_per_columns)
     Tb_row = W.spot_Tb(spec.nx, Tb, n_spots, spec.seed)
     gam = np.full(spec.nx, -spec.gamma_frac * d.psi_L)
-    bc = dict(T_top=d.Tsat, Tb=Tb_row, gamma_bot=gam, gamma_top=gam.copy())
+    bc = dict(T_top=d.Tsat, Tb=Tb_row, gamma_bot=gam, gamma_top=np.full(spec.nx, -d.psi_V))
     rho = W.layered_rho(spec.nx, spec.nyf, int(round(spec.liquid_fraction * spec.nyf)), d.rho_L, d.rho_V)
     T = W.thermal_init(spec.nx, spec.nys, spec.nyf, d.Tsat, Tb_row)
     return bc, rho, T

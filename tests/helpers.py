@@ -36,13 +36,15 @@ def params(nx, nyf, nys, **over):
 def pool_case(nx, nyf, nys, superheat=0.1, n_spots=4, seed=0, y0=None, gamma_frac=0.7, **over):
     """Pool-boiling start: liquid below y0 at the Maxwell density, vapour above,
     T = Tsat everywhere except the heater bottom at Tsat + superheat*Tc with
-    seeded +2% hot spots; uniform wall adhesion gamma = -gamma_frac * psi_L."""
+    seeded +2% hot spots; heater-wall adhesion gamma = -gamma_frac * psi_L,
+    vapour-neutral top wall gamma = -psi_V; gravity for the domain height."""
+    over.setdefault("g", W.gravity_for_height(nyf))
     P, d = params(nx, nyf, nys, **over)
     y0 = int(round(0.4 * nyf)) if y0 is None else y0
     Tb = d["Tsat"] + superheat * d["Tc"]
     Tb_row = W.spot_Tb(nx, Tb, n_spots, seed) if n_spots > 0 else np.full(nx, Tb)
     gam = np.full(nx, -gamma_frac * d["psi_L"])
-    bc = dict(T_top=d["Tsat"], Tb=Tb_row, gamma_bot=gam, gamma_top=gam.copy())
+    bc = dict(T_top=d["Tsat"], Tb=Tb_row, gamma_bot=gam, gamma_top=np.full(nx, -d["psi_V"]))
     rho = W.layered_rho(nx, nyf, y0, d["rho_L"], d["rho_V"])
     T = W.thermal_init(nx, nys, nyf, d["Tsat"], Tb_row)
     return P, d, bc, rho, T

@@ -51,6 +51,11 @@ def test_host_eos_helpers_match_oracle():
         rl, rv = pb.coexistence(a, P["b"], P["R"], P["omega"], Tc, 0.86 * Tc)
         assert rl == pytest.approx(d["rho_L"], rel=1e-10)
         assert rv == pytest.approx(d["rho_V"], rel=1e-10)
+        from oracle import eos
+        h = pb.latent_heat(a, P["b"], P["R"], P["omega"], Tc, 0.86 * Tc)
+        assert h == pytest.approx(eos.latent_heat(0.86 * d["Tc"], a, P["b"], P["R"], P["omega"], d["Tc"]), rel=1e-6)
+        psi = pb.eos_psi(a, P["b"], P["R"], P["omega"], Tc, -1.0, rl, 0.86 * Tc)
+        assert psi == pytest.approx(d["psi_L"], rel=1e-10)
 
 
 def test_invalid_configs_rejected_without_gpu():

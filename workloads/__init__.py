@@ -23,6 +23,16 @@ BASE_PARAMS = dict(
 )
 T_SAT_OVER_TC = 0.86          # Section 3.1
 RHO_S_OVER_RHO_L = 3.0        # Section 3.1
+REF_FLUID_HEIGHT = 300        # Section 3.1: 400 x 300 fluid domain with g = 5e-5
+
+
+def gravity_for_height(nyf, g=BASE_PARAMS["g"]):
+    """Gravity for a fluid domain of nyf rows: the printed g up to the
+    paper's 300-row height, scaled down by 300/nyf above it so that the
+    hydrostatic head of the buoyancy term (rho - rho_bar) g across the domain
+    never exceeds the paper's (taller columns of vapour otherwise compress
+    to liquid density at the top and rarefy to zero at the bottom)."""
+    return float(g) * min(1.0, REF_FLUID_HEIGHT / float(nyf))
 
 
 def layered_rho(nx, nyf, y0, rho_l, rho_v):
