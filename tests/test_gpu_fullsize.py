@@ -1,0 +1,63 @@
+"""Parity at the workload sizes, and the long-run heat-flux statistic.
+
+* 400x400 fluid + 400x20 heater (paper-scale job), FP64 and FP32-deviation
+  storage, 100 steps against the oracle, every field.
+* 4096x2048 fluid + 4096x64 heater (roofline case) in the launch
+  configuration the benchmark times (autotuned tiles are bit-identical to the
+  default, checked elsewhere), FP32-deviation storage, 2 steps against the
+  oracle on the whole domain, plus mass conservation after 200 steps.
+* Long runs are chaotic: the FP32-deviation GPU run and the FP64 oracle are
+  compared only through the time-mean wall heat flux of Eq. 38 at each
+  superheat, within 3%.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_common import compare, gpu_domain, oracle_domain, run_pair
+from helpers import pool_case
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+TOL = {0: 1e-11, 1: 2e-5}
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_paper_scale_400x400(precision):
+    P, d, bc, rho, T = pool_case(400, 400, 20, superheat=0.15, n_spots=6, seed=11, y0=160)
+    g, o = run_pair(P, bc, rho, T, steps=100, precision=precision, window=(10, 101, 10))
+    errs = compare(g, o)
+    print("400x400 prec", precision, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert all(v <= TOL[precision] for v in errs.values()), errs
+    assert g["flux"]["q_bottom_mean"] == pytest.approx(o["flux"]["q_bottom_mean"], rel=10 * TOL[precision])
+
+
+def test_roofline_case_full_domain():
+    nx, nyf, nys = 4096, 2048, 64
+    P, d, bc, rho, T = pool_case(nx, nyf, nys, superheat=0.1, n_spots=nx // 64, seed=0, y0=int(round(0.4 * nyf)))
+    print("roofline case: 2 steps, FP32-deviation, whole domain", flush=True)
+    g, o = run_pair(P, bc, rho, T, steps=2, precision=1)
+    errs = compare(g, o)
+    print("4096x2048", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert all(v <= TOL[1] for v in errs.values()), errs
+    # property that holds at any length: mass is conserved (FP32 storage
+    # rounding of the deviations only)
+    dom = gpu_domain(P, bc, rho, T, precision=1, tile=(64, 8), thermal_tile=0)
+    m0 = rho.sum()
+    dom.step(200)
+    dom.sync()
+    m1 = dom.read(with_f=False)["rho"].sum()
+    assert abs(m1 - m0) / m0 < 1e-9
+    dom.close()
+
+
+@pytest.mark.parametrize("superheat", [0.05, 0.2])
+def test_long_run_mean_heat_flux_within_3pct(superheat):
+    """100x100 fluid + 100x10 heater, 3000 steps, Eq. 38 mean of q_bottom over
+    steps [1500, 3000) sampled every 10: FP32-deviation GPU vs FP64 oracle."""
+    P, d, bc, rho, T = pool_case(100, 100, 10, superheat=superheat, n_spots=4, seed=0, y0=40)
+    g, o = run_pair(P, bc, rho, T, steps=3000, precision=1, window=(1500, 3001, 10))
+    qg, qo = g["flux"]["q_bottom_mean"], o["flux"]["q_bottom_mean"]
+    print(f"superheat {superheat}: q_gpu {qg:.6e} q_oracle {qo:.6e} rel {abs(qg - qo) / abs(qo):.2e}", flush=True)
+    assert g["flux"]["n_samples"] == o["flux"]["n_samples"] == 150
+    assert abs(qg - qo) <= 0.03 * abs(qo)
