@@ -69,6 +69,13 @@ class Flux(C.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() (no fallback exists)")
+    # torch bundles its own HIP runtime under a different file name; loading it
+    # first makes the library bind to that same runtime (one runtime per
+    # process, so torch-allocated device memory is valid for the library)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     vp, dp, i64, i32 = C.c_void_p, C.POINTER(C.c_double), C.c_int64, C.c_int32
     sig = {
