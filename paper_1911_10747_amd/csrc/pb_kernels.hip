@@ -345,8 +345,18 @@ struct Coef9 {
     double k0, k1, k2, k3, k4, k5, k6, k7, k8, beta;
 };
 
-__device__ __forceinline__ double from_left(double v) { return __shfl_up(v, 1); }    // value at x-1
-__device__ __forceinline__ double from_right(double v) { return __shfl_down(v, 1); } // value at x+1
+// Lane exchange with DPP wave shifts (a VALU move, no LDS round trip): wave_shr:1
+// gives lane i the value of lane i-1 (column x-1), wave_shl:1 that of lane i+1.
+// The end lanes receive 0; they are halo columns whose results are discarded.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double from_left(double v) { return dpp_move<0x138>(v); }   // value at x-1
+__device__ __forceinline__ double from_right(double v) { return dpp_move<0x130>(v); }  // value at x+1
 
 // harmonic-mean link conductance; a negative value marks the T_top row, whose
 // links take the conductance of the other node
@@ -403,9 +413,28 @@ __device__ __forceinline__ double apply9(const Coef9 &c, int kind, double Sc, do
     return K;
 }
 
-template <int H, int WPE>
+// Operator rows of the three previous rows live in LDS (each lane touches only
+// its own column, so no barriers are needed); the row being built stays in
+// registers.  Rows n+1 and n+2 are prefetched from HBM.
+__device__ __forceinline__ void cf_store(double *slot, const Coef9 &c, int lane) {
+    slot[0 * 64 + lane] = c.k0; slot[1 * 64 + lane] = c.k1; slot[2 * 64 + lane] = c.k2;
+    slot[3 * 64 + lane] = c.k3; slot[4 * 64 + lane] = c.k4; slot[5 * 64 + lane] = c.k5;
+    slot[6 * 64 + lane] = c.k6; slot[7 * 64 + lane] = c.k7; slot[8 * 64 + lane] = c.k8;
+    slot[9 * 64 + lane] = c.beta;
+}
+__device__ __forceinline__ Coef9 cf_load(const double *slot, int lane) {
+    Coef9 c;
+    c.k0 = slot[0 * 64 + lane]; c.k1 = slot[1 * 64 + lane]; c.k2 = slot[2 * 64 + lane];
+    c.k3 = slot[3 * 64 + lane]; c.k4 = slot[4 * 64 + lane]; c.k5 = slot[5 * 64 + lane];
+    c.k6 = slot[6 * 64 + lane]; c.k7 = slot[7 * 64 + lane]; c.k8 = slot[8 * 64 + lane];
+    c.beta = slot[9 * 64 + lane];
+    return c;
+}
+
+template <int H, int WPE, int UNR>
 __global__ __launch_bounds__(64, WPE) void k_thermal_sweep(const PbDesc *const *__restrict__ dps,
-                                                       const PbTile *__restrict__ tiles, int ntiles, int k) {
+                                                            const PbTile *__restrict__ tiles, int ntiles, int k) {
+    __shared__ double s_cf[3][10 * 64];
     const int lane = threadIdx.x;
     for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
         const PbTile te = tiles[tl];
@@ -437,17 +466,25 @@ __global__ __launch_bounds__(64, WPE) void k_thermal_sweep(const PbDesc *const *
         double s2_3 = 0.0, s2L_3 = 0.0, s2R_3 = 0.0, s2_4 = 0.0, s2L_4 = 0.0, s2R_4 = 0.0;
         double s3_4 = 0.0, s3L_4 = 0.0, s3R_4 = 0.0, s3_5 = 0.0, s3L_5 = 0.0, s3R_5 = 0.0;
         double acc_2 = 0.0, acc_3 = 0.0, acc_4 = 0.0;
-        Coef9 cf_2{}, cf_3{}, cf_4{};
         int kd_2 = KIND_NONE, kd_3 = KIND_NONE, kd_4 = KIND_NONE;
         bool bad = false;
+        {
+            const Coef9 z{};
+            for (int q = 0; q < 3; ++q) cf_store(s_cf[q], z, lane);
+        }
 
         const int nbeg = te.y0 - 4, nend = te.y0 + H + 3;
-        RowIn nxt = load_row(d, Tin, rhog, vxg, vyg, nbeg, xg, pery);
-#pragma unroll 4
+        RowIn nx1 = load_row(d, Tin, rhog, vxg, vyg, nbeg, xg, pery);
+        RowIn nx2 = load_row(d, Tin, rhog, vxg, vyg, nbeg + 1, xg, pery);
+#pragma unroll UNR
         for (int j = 0; j < H + 8; ++j) {
             const int n = nbeg + j;
-            const RowIn cur = nxt;
-            if (n < nend) nxt = load_row(d, Tin, rhog, vxg, vyg, n + 1, xg, pery);
+            const RowIn cur = nx1;
+            nx1 = nx2;
+            if (n + 2 <= nend) nx2 = load_row(d, Tin, rhog, vxg, vyg, n + 2, xg, pery);
+            double *slot_2 = s_cf[(j + 1) % 3];     // operator of row n-2
+            double *slot_3 = s_cf[j % 3];           // operator of row n-3
+            double *slot_4 = s_cf[(j + 2) % 3];     // operator of row n-4; then reused for row n-1
 
             // new row n: neighbours across lanes
             const double lamL = from_left(cur.lam), lamR = from_right(cur.lam);
@@ -492,17 +529,17 @@ __global__ __launch_bounds__(64, WPE) void k_thermal_sweep(const PbDesc *const *
             const double acc1 = K1;
             const double s1L = from_left(s1), s1R = from_right(s1);
             // stage 2 on row n-2 (input s1 rows n-3, n-2, n-1)
-            const double K2 = apply9(cf_2, kd_2, s1_2, s1R_2, s1L_2, s1, s1R, s1L, s1_3, s1R_3, s1L_3);
+            const double K2 = apply9(cf_load(slot_2, lane), kd_2, s1_2, s1R_2, s1L_2, s1, s1R, s1L, s1_3, s1R_3, s1L_3);
             const double s2 = T0_2 + 0.5 * K2;
             const double acc2 = acc_2 + 2.0 * K2;
             const double s2L = from_left(s2), s2R = from_right(s2);
             // stage 3 on row n-3 (input s2 rows n-4, n-3, n-2)
-            const double K3 = apply9(cf_3, kd_3, s2_3, s2R_3, s2L_3, s2, s2R, s2L, s2_4, s2R_4, s2L_4);
+            const double K3 = apply9(cf_load(slot_3, lane), kd_3, s2_3, s2R_3, s2L_3, s2, s2R, s2L, s2_4, s2R_4, s2L_4);
             const double s3 = T0_3 + K3;
             const double acc3 = acc_3 + 2.0 * K3;
             const double s3L = from_left(s3), s3R = from_right(s3);
             // stage 4 and the update on row e = n-4 (input s3 rows n-5, n-4, n-3)
-            const double K4 = apply9(cf_4, kd_4, s3_4, s3R_4, s3L_4, s3, s3R, s3L, s3_5, s3R_5, s3L_5);
+            const double K4 = apply9(cf_load(slot_4, lane), kd_4, s3_4, s3R_4, s3L_4, s3, s3R, s3L, s3_5, s3R_5, s3L_5);
             const int e = n - 4;
             if (out_lane && e >= te.y0 && e < te.y0 + H && e >= 0 && e < d.nr) {
                 double Tn;
@@ -515,6 +552,7 @@ __global__ __launch_bounds__(64, WPE) void k_thermal_sweep(const PbDesc *const *
                 Tout[(uint32_t)e * (uint32_t)d.pitch + (uint32_t)xg] = Tn;
                 bad = bad || !(Tn - Tn == 0.0);
             }
+            cf_store(slot_4, cf, lane);             // row n-1 takes the slot of row n-4
 
             // shift the windows by one row
             s3_5 = s3_4; s3L_5 = s3L_4; s3R_5 = s3R_4;
@@ -524,9 +562,7 @@ __global__ __launch_bounds__(64, WPE) void k_thermal_sweep(const PbDesc *const *
             s1_3 = s1_2; s1L_3 = s1L_2; s1R_3 = s1R_2;
             s1_2 = s1; s1L_2 = s1L; s1R_2 = s1R;
             acc_4 = acc3; acc_3 = acc2; acc_2 = acc1;
-            cf_4 = cf_3; kd_4 = kd_3;
-            cf_3 = cf_2; kd_3 = kd_2;
-            cf_2 = cf; kd_2 = kind_1;
+            kd_4 = kd_3; kd_3 = kd_2; kd_2 = kind_1;
             T0_4 = T0_3; T0_3 = T0_2;
             T0_2 = T0_1; T0L_2 = T0L_1; T0R_2 = T0R_1;
             T0_1 = cur.T0; T0L_1 = T0L; T0R_1 = T0R;
@@ -649,7 +685,9 @@ __global__ void k_advance(PbDesc *const *__restrict__ dps, int ndom, int nsteps)
 // Flow tile variants: (BX, BY) with BX * BY threads per block.
 static const int kFlowShapes[][2] = {{64, 4}, {64, 8}, {32, 8}, {128, 4}, {32, 16}, {64, 16}};
 // column sweeps of 56 written columns x H rows
-static const int kThermalShapes[][2] = {{56, 32}, {56, 64}, {56, 16}, {56, 8}};
+// variant 3 keeps the loop (unrolled by 3, operator ring in LDS); the others
+// unroll the whole strip so the ring lives in registers
+static const int kThermalShapes[][2] = {{56, 20}, {56, 24}, {56, 16}, {56, 32}, {56, 28}};
 
 int pb_flow_variants() { return (int)(sizeof(kFlowShapes) / sizeof(kFlowShapes[0])); }
 int pb_thermal_variants() { return (int)(sizeof(kThermalShapes) / sizeof(kThermalShapes[0])); }
@@ -695,10 +733,11 @@ hipError_t pb_launch_flow(int prec, int mode, int variant, const PbDesc *const *
 hipError_t pb_launch_thermal(int variant, const PbDesc *const *dps, const PbTile *d_tiles, int ntiles, int grid, int k,
                              hipStream_t s) {
     switch (variant) {
-        case 0: hipLaunchKernelGGL((k_thermal_sweep<32, 2>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
-        case 1: hipLaunchKernelGGL((k_thermal_sweep<64, 2>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
-        case 2: hipLaunchKernelGGL((k_thermal_sweep<16, 2>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
-        case 3: hipLaunchKernelGGL((k_thermal_sweep<8, 2>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
+        case 0: hipLaunchKernelGGL((k_thermal_sweep<20, 2, 28>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
+        case 1: hipLaunchKernelGGL((k_thermal_sweep<24, 2, 32>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
+        case 2: hipLaunchKernelGGL((k_thermal_sweep<16, 2, 24>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
+        case 3: hipLaunchKernelGGL((k_thermal_sweep<32, 2, 3>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
+        case 4: hipLaunchKernelGGL((k_thermal_sweep<28, 2, 36>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
