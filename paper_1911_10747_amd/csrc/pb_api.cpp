@@ -83,8 +83,8 @@ Layout layout_of(const pb_config &c) {
     L.f[1] = take(9 * nf * es);
     L.rho[0] = take(nf * 8);
     L.rho[1] = take(nf * 8);
-    L.vx = take(nf * 8);
-    L.vy = take(nf * 8);
+    L.vx = take(nf * es);   // velocity stored like the populations: FP64 or FP32
+    L.vy = take(nf * es);
     L.T[0] = take(nt * 8);
     L.T[1] = take(nt * 8);
     L.Tb = take((size_t)c.nx * 8);
@@ -242,7 +242,7 @@ int enqueue_steps(pb_domain *d, int64_t n) {
         for (int k = 0; k < m; ++k) {
             if (!frozen) PB_HIP(pb_launch_flow(d->cfg.precision, PB_MODE_STEP, d->fvar, dp, d->dtiles_flow, d->nt_flow,
                                                d->nt_flow, k, d->stream));
-            if (!iso) PB_HIP(pb_launch_thermal(d->tvar, dp, d->dtiles_th, d->nt_th, d->nt_th, k, d->stream));
+            if (!iso) PB_HIP(pb_launch_thermal(d->cfg.precision, d->tvar, dp, d->dtiles_th, d->nt_th, d->nt_th, k, d->stream));
             const int64_t tk = d->t + k + 1;
             if (sampling && tk >= d->hd.fl_ta && tk < d->hd.fl_tb && (tk - d->hd.fl_ta) % d->hd.fl_every == 0)
                 PB_HIP(pb_launch_flux(dp, 1, k, d->stream));
@@ -317,8 +317,8 @@ int pb_create_domain(const pb_config *cfg, void *stream, void *dev_mem, size_t d
         h.rho[b] = (double *)(d->base + L.rho[b]);
         h.T[b] = (double *)(d->base + L.T[b]);
     }
-    h.vx = (double *)(d->base + L.vx);
-    h.vy = (double *)(d->base + L.vy);
+    h.vx = d->base + L.vx;
+    h.vy = d->base + L.vy;
     h.Tb = (const double *)(d->base + L.Tb);
     h.Tb_alt = (const double *)(d->base + L.Tba);
     h.gbot = (const double *)(d->base + L.gb);
@@ -595,7 +595,7 @@ int pb_profile_steps(pb_domain *d, int64_t n, double *avg_ms) {
             err = pb_launch_flow(d->cfg.precision, PB_MODE_STEP, d->fvar, dp, d->dtiles_flow, d->nt_flow, d->nt_flow, k,
                                  d->stream);
         if (err == hipSuccess) err = hipEventRecord(ev[2 * k + 1], d->stream);
-        if (err == hipSuccess && !iso) err = pb_launch_thermal(d->tvar, dp, d->dtiles_th, d->nt_th, d->nt_th, k, d->stream);
+        if (err == hipSuccess && !iso) err = pb_launch_thermal(d->cfg.precision, d->tvar, dp, d->dtiles_th, d->nt_th, d->nt_th, k, d->stream);
         const int64_t tk = d->t + k + 1;
         if (err == hipSuccess && sampling && tk >= d->hd.fl_ta && tk < d->hd.fl_tb &&
             (tk - d->hd.fl_ta) % d->hd.fl_every == 0)
@@ -714,7 +714,7 @@ static int batch_enqueue(pb_batch *b, int nsteps) {
     const int nd = (int)b->doms.size();
     for (int k = 0; k < nsteps; ++k) {
         PB_HIP(pb_launch_flow(b->prec, PB_MODE_STEP, b->fvar, dp, b->dtiles_flow, b->nt_flow, b->grid_flow, k, b->stream));
-        PB_HIP(pb_launch_thermal(b->tvar, dp, b->dtiles_th, b->nt_th, b->grid_th, k, b->stream));
+        PB_HIP(pb_launch_thermal(b->prec, b->tvar, dp, b->dtiles_th, b->nt_th, b->grid_th, k, b->stream));
         if (b->any_flux) PB_HIP(pb_launch_flux(dp, nd, k, b->stream));
     }
     PB_HIP(pb_launch_advance(b->dptrs, nd, nsteps, b->stream));

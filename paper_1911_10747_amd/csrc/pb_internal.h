@@ -21,7 +21,7 @@ struct PbDesc {
     // state
     void *f[2];          // populations [9][nyf][pitch], double or float (deviation)
     double *rho[2];      // rho(t) written by the flow kernel, [nyf][pitch]
-    double *vx, *vy;     // v(t) written by the flow kernel, [nyf][pitch]
+    void *vx, *vy;       // v(t) written by the flow kernel, [nyf][pitch]; FP32 with FP32 storage
     double *T[2];        // temperature [nr][pitch]
     // boundary data [nx]
     const double *Tb, *Tb_alt, *gbot, *gtop;
@@ -51,8 +51,8 @@ enum { PB_MODE_STEP = 0, PB_MODE_READ = 1 };
 // d_descs is a device array of device pointers to the domains' descriptors.
 hipError_t pb_launch_flow(int prec, int mode, int tile_variant, const PbDesc *const *d_descs, const PbTile *d_tiles,
                           int ntiles, int grid, int k, hipStream_t s);
-hipError_t pb_launch_thermal(int tile_variant, const PbDesc *const *d_descs, const PbTile *d_tiles, int ntiles,
-                             int grid, int k, hipStream_t s);
+hipError_t pb_launch_thermal(int prec, int tile_variant, const PbDesc *const *d_descs, const PbTile *d_tiles,
+                             int ntiles, int grid, int k, hipStream_t s);
 hipError_t pb_launch_flux(const PbDesc *const *d_descs, int ndom, int k, hipStream_t s);
 hipError_t pb_launch_advance(PbDesc *const *d_descs, int ndom, int nsteps, hipStream_t s);
 hipError_t pb_launch_init(int prec, const PbDesc *d_desc, int par, hipStream_t s);

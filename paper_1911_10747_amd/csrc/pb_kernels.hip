@@ -298,8 +298,8 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
             store_pop<FT>(fout, plane, oidx, 7, cd - a3 - a4 - a5 - a6 + a8, rho);
             store_pop<FT>(fout, plane, oidx, 8, cd + a3 + a4 - a5 - a6 - a8, rho);
             gcast_w<double>(d.rho[pout])[oidx] = rho;
-            gcast_w<double>(d.vx)[oidx] = vx;
-            gcast_w<double>(d.vy)[oidx] = vy;
+            gcast_w<FT>(d.vx)[oidx] = (FT)vx;      // FP32 with FP32 storage
+            gcast_w<FT>(d.vy)[oidx] = (FT)vy;
         }
         if (bad || !(rho == rho) || !(vx - vx == 0.0) || !(vy - vy == 0.0)) *s_bad = 1;
     }
@@ -372,8 +372,9 @@ struct RowIn {
     double T0, lam, rho, vx, vy;
 };
 
+template <typename VT>
 __device__ __forceinline__ RowIn load_row(cdesc &d, const double PB_GAS *Tin, const double PB_GAS *rho,
-                                          const double PB_GAS *vxg, const double PB_GAS *vyg, int n, int xg, bool pery) {
+                                          const VT PB_GAS *vxg, const VT PB_GAS *vyg, int n, int xg, bool pery) {
     RowIn r{KIND_NONE, 0.0, 0.0, 0.0, 0.0, 0.0};
     int rr = n;
     if (pery) {
@@ -431,7 +432,7 @@ __device__ __forceinline__ Coef9 cf_load(const double *slot, int lane) {
     return c;
 }
 
-template <int H, int WPE, int UNR>
+template <typename VT, int H, int WPE, int UNR>
 __global__ __launch_bounds__(64, WPE) void k_thermal_sweep(const PbDesc *const *__restrict__ dps,
                                                             const PbTile *__restrict__ tiles, int ntiles, int k) {
     __shared__ double s_cf[3][10 * 64];
@@ -445,8 +446,8 @@ __global__ __launch_bounds__(64, WPE) void k_thermal_sweep(const PbDesc *const *
         const double PB_GAS *Tin = gcast<double>(d.T[pin]);
         double PB_GAS *Tout = gcast_w<double>(d.T[pout]);
         const double PB_GAS *rhog = gcast<double>(d.rho[pout]);   // rho(t) written by this step's flow
-        const double PB_GAS *vxg = gcast<double>(d.vx);
-        const double PB_GAS *vyg = gcast<double>(d.vy);
+        const VT PB_GAS *vxg = gcast<VT>(d.vx);
+        const VT PB_GAS *vyg = gcast<VT>(d.vy);
         int xg = (te.x0 - 4 + lane) % d.nx;
         if (xg < 0) xg += d.nx;
         const bool out_lane = lane >= 4 && lane < 60 && (te.x0 + lane - 4) < d.nx;
@@ -474,14 +475,14 @@ __global__ __launch_bounds__(64, WPE) void k_thermal_sweep(const PbDesc *const *
         }
 
         const int nbeg = te.y0 - 4, nend = te.y0 + H + 3;
-        RowIn nx1 = load_row(d, Tin, rhog, vxg, vyg, nbeg, xg, pery);
-        RowIn nx2 = load_row(d, Tin, rhog, vxg, vyg, nbeg + 1, xg, pery);
+        RowIn nx1 = load_row<VT>(d, Tin, rhog, vxg, vyg, nbeg, xg, pery);
+        RowIn nx2 = load_row<VT>(d, Tin, rhog, vxg, vyg, nbeg + 1, xg, pery);
 #pragma unroll UNR
         for (int j = 0; j < H + 8; ++j) {
             const int n = nbeg + j;
             const RowIn cur = nx1;
             nx1 = nx2;
-            if (n + 2 <= nend) nx2 = load_row(d, Tin, rhog, vxg, vyg, n + 2, xg, pery);
+            if (n + 2 <= nend) nx2 = load_row<VT>(d, Tin, rhog, vxg, vyg, n + 2, xg, pery);
             double *slot_2 = s_cf[(j + 1) % 3];     // operator of row n-2
             double *slot_3 = s_cf[j % 3];           // operator of row n-3
             double *slot_4 = s_cf[(j + 2) % 3];     // operator of row n-4; then reused for row n-1
@@ -648,8 +649,8 @@ __global__ __launch_bounds__(256) void k_init(const PbDesc *__restrict__ dp, int
         const size_t idx = (size_t)y * d.pitch + x;
         const double r = d.rho[par][idx];
         d.rho[par ^ 1][idx] = r;
-        d.vx[idx] = 0.0;
-        d.vy[idx] = 0.0;
+        ((FT *)d.vx)[idx] = (FT)0;
+        ((FT *)d.vy)[idx] = (FT)0;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             const int xd = wrap_once(x + kEX[i], d.nx);
@@ -685,9 +686,8 @@ __global__ void k_advance(PbDesc *const *__restrict__ dps, int ndom, int nsteps)
 // Flow tile variants: (BX, BY) with BX * BY threads per block.
 static const int kFlowShapes[][2] = {{64, 4}, {64, 8}, {32, 8}, {128, 4}, {32, 16}, {64, 16}};
 // column sweeps of 56 written columns x H rows
-// variant 3 keeps the loop (unrolled by 3, operator ring in LDS); the others
-// unroll the whole strip so the ring lives in registers
-static const int kThermalShapes[][2] = {{56, 20}, {56, 24}, {56, 16}, {56, 32}, {56, 28}};
+// the whole strip is unrolled so the operator ring lives in registers
+static const int kThermalShapes[][2] = {{56, 28}, {56, 20}, {56, 24}, {56, 16}};
 
 int pb_flow_variants() { return (int)(sizeof(kFlowShapes) / sizeof(kFlowShapes[0])); }
 int pb_thermal_variants() { return (int)(sizeof(kThermalShapes) / sizeof(kThermalShapes[0])); }
@@ -730,17 +730,23 @@ hipError_t pb_launch_flow(int prec, int mode, int variant, const PbDesc *const *
                                 : launch_flow_t<float, PB_MODE_STEP>(variant, d_descs, d_tiles, ntiles, grid, k, s);
 }
 
-hipError_t pb_launch_thermal(int variant, const PbDesc *const *dps, const PbTile *d_tiles, int ntiles, int grid, int k,
-                             hipStream_t s) {
+template <typename VT>
+static hipError_t launch_thermal_t(int variant, const PbDesc *const *dps, const PbTile *d_tiles, int ntiles, int grid,
+                                   int k, hipStream_t s) {
     switch (variant) {
-        case 0: hipLaunchKernelGGL((k_thermal_sweep<20, 2, 28>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
-        case 1: hipLaunchKernelGGL((k_thermal_sweep<24, 2, 32>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
-        case 2: hipLaunchKernelGGL((k_thermal_sweep<16, 2, 24>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
-        case 3: hipLaunchKernelGGL((k_thermal_sweep<32, 2, 3>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
-        case 4: hipLaunchKernelGGL((k_thermal_sweep<28, 2, 36>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
+        case 0: hipLaunchKernelGGL((k_thermal_sweep<VT, 28, 2, 36>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
+        case 1: hipLaunchKernelGGL((k_thermal_sweep<VT, 20, 2, 28>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
+        case 2: hipLaunchKernelGGL((k_thermal_sweep<VT, 24, 2, 32>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
+        case 3: hipLaunchKernelGGL((k_thermal_sweep<VT, 16, 2, 24>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t pb_launch_thermal(int prec, int variant, const PbDesc *const *dps, const PbTile *d_tiles, int ntiles,
+                             int grid, int k, hipStream_t s) {
+    return prec == 0 ? launch_thermal_t<double>(variant, dps, d_tiles, ntiles, grid, k, s)
+                     : launch_thermal_t<float>(variant, dps, d_tiles, ntiles, grid, k, s);
 }
 
 hipError_t pb_launch_flux(const PbDesc *const *d_descs, int ndom, int k, hipStream_t s) {
