@@ -42,11 +42,17 @@ def algorithmic_bytes(nx, nyf, nys, precision):
     return per_fluid * nx * nyf + 16 * nx * nys
 
 
-def load_traffic(kernel_key):
-    """HBM traffic per step measured with rocprofv3 PMC counters, if the
-    measurement was taken on the current kernel source (hash match)."""
+TRAFFIC_FILES = {"roofline": "pmc_traffic_step_4096x2048_fp32dev.txt"}
+
+
+def load_traffic(workload):
+    """HBM bytes per step (both launches) measured with rocprofv3 FETCH_SIZE /
+    WRITE_SIZE and scaled by a copy-kernel calibration, if the measurement was
+    taken on the current kernel source (hash match); else None."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if workload not in TRAFFIC_FILES:
+        return None
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILES[workload])
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -54,7 +60,7 @@ def load_traffic(kernel_key):
     src = open(os.path.join(ROOT, "paper_1911_10747_amd", "csrc", "pb_kernels.hip"), "rb").read()
     if rec.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
         return None
-    return rec.get(kernel_key)
+    return rec.get("roofline_bytes_per_step")
 
 
 def cpu_baseline(nx, nyf, nys, steps):
@@ -197,7 +203,7 @@ def main():
     alg = algorithmic_bytes(nx, nyf, nys, prec)
     kern_ms = prof["flow_ms"] + prof["thermal_ms"]
     achieved = alg / (kern_ms * 1e-3) / 1e9
-    traffic = load_traffic(f"{args.workload}_bytes_per_step")
+    traffic = load_traffic(args.workload)
     out = {
         "metric": "MLUPS (fused pool-boiling step, fluid-node updates per second) and fraction of HBM peak",
         "value": round(mlups, 1),
