@@ -133,6 +133,23 @@ __device__ __forceinline__ void pull_inner(const FT PB_GAS *fin, const double PB
     }
 }
 
+// Same, with the reference densities of the FP32 decode taken from an LDS
+// copy of rho(t-1) over the tile plus two rings (row stride RW, node at (lx, ly)
+// of that copy).
+template <typename FT, int RW>
+__device__ __forceinline__ void pull_inner_lds(const FT PB_GAS *fin, const double *s_rho, uint32_t plane,
+                                               uint32_t pitch, uint32_t idx, int lx, int ly, double f[9]) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const uint32_t src = idx - (uint32_t)(kEY[i] * (int)pitch) - (uint32_t)kEX[i];
+        const FT v = (fin + (uint32_t)i * plane)[src];
+        if constexpr (std::is_same<FT, float>::value)
+            f[i] = kW[i] * s_rho[(ly - kEY[i]) * RW + lx - kEX[i]] + (double)v;
+        else
+            f[i] = v;
+    }
+}
+
 template <typename FT>
 __device__ __forceinline__ void store_pop(FT PB_GAS *fout, uint32_t plane, uint32_t idx, int i, double fs,
                                           double rho) {
@@ -147,7 +164,10 @@ __device__ __forceinline__ void store_pop(FT PB_GAS *fout, uint32_t plane, uint3
 // velocity and collision on the tile.  INNER: every node of the tile and its
 // ring is at least two nodes from the x edges and from the walls.
 template <typename FT, int BX, int BY, int MODE, bool INNER>
-__device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, double *s_psi, int *s_bad) {
+__device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, double *s_psi, double *s_rho,
+                                          int *s_bad) {
+    constexpr int RW = BX + 4, RH = BY + 4;        // rho(t-1) copy: tile plus two rings
+    constexpr bool RLDS = INNER && std::is_same<FT, float>::value;
     constexpr int LW = BX + 2, LH = BY + 2;
     constexpr int NHALO = 2 * LW + 2 * BY;
     const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
@@ -160,6 +180,14 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
     const uint32_t pitch = (uint32_t)d.pitch, plane = (uint32_t)d.nyf * pitch;
     const uint32_t toff = (uint32_t)d.nys * pitch;           // fluid row 0 in the T array
     bool bad = false;
+    if constexpr (RLDS) {
+        // all these nodes lie inside the fluid (the tile is two nodes from every edge)
+        for (int q = threadIdx.x; q < RW * RH; q += BX * BY) {
+            const int qx = q % RW, qy = q / RW;
+            s_rho[q] = rin[(uint32_t)(te.y0 - 2 + qy) * pitch + (uint32_t)(te.x0 - 2 + qx)];
+        }
+        __syncthreads();
+    }
 
     // this thread's node; positions past the edge wrap once so that the first
     // column/row beyond holds the periodic neighbour
@@ -171,7 +199,8 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
     double f[9], rho = 0.0, jx = 0.0, jy = 0.0, psi = 0.0;
     const uint32_t idx = (uint32_t)yw * pitch + (uint32_t)xw;
     if (live) {
-        if (INNER) pull_inner<FT>(fin, rin, plane, pitch, idx, f);
+        if constexpr (RLDS) pull_inner_lds<FT, RW>(fin, s_rho, plane, pitch, idx, tx + 2, ty + 2, f);
+        else if (INNER) pull_inner<FT>(fin, rin, plane, pitch, idx, f);
         else pull_node<FT>(d, fin, rin, xw, yw, pery, f);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
@@ -203,7 +232,8 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
         if (ok) {
             double fh[9], rh = 0.0;
             const uint32_t hidx = (uint32_t)yh * pitch + (uint32_t)xh;
-            if (INNER) pull_inner<FT>(fin, rin, plane, pitch, hidx, fh);
+            if constexpr (RLDS) pull_inner_lds<FT, RW>(fin, s_rho, plane, pitch, hidx, lx + 1, ly + 1, fh);
+            else if (INNER) pull_inner<FT>(fin, rin, plane, pitch, hidx, fh);
             else pull_node<FT>(d, fin, rin, xh, yh, pery, fh);
 #pragma unroll
             for (int i = 0; i < 9; ++i) rh += fh[i];
@@ -311,6 +341,7 @@ __global__ __launch_bounds__(BX *BY) void k_flow(const PbDesc *const *__restrict
     constexpr int LW = BX + 2, LH = BY + 2;
     static_assert(2 * LW + 2 * BY <= BX * BY, "halo larger than block");
     __shared__ double s_psi[LW * LH];
+    __shared__ double s_rho[(BX + 4) * (BY + 4)];
     __shared__ int s_bad;
     for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
         const PbTile te = tiles[tl];
@@ -318,8 +349,8 @@ __global__ __launch_bounds__(BX *BY) void k_flow(const PbDesc *const *__restrict
         if (threadIdx.x == 0) s_bad = 0;
         const bool inner = !(d.flags & F_PERY) && te.x0 >= 2 && te.x0 + BX + 2 <= d.nx && te.y0 >= 2 &&
                            te.y0 + BY + 2 <= d.nyf;
-        if (inner) flow_tile<FT, BX, BY, MODE, true>(d, te, k, s_psi, &s_bad);
-        else flow_tile<FT, BX, BY, MODE, false>(d, te, k, s_psi, &s_bad);
+        if (inner) flow_tile<FT, BX, BY, MODE, true>(d, te, k, s_psi, s_rho, &s_bad);
+        else flow_tile<FT, BX, BY, MODE, false>(d, te, k, s_psi, s_rho, &s_bad);
         __syncthreads();
         if (threadIdx.x == 0 && s_bad) flag_error(d);
         __syncthreads();
