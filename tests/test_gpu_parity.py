@@ -178,6 +178,47 @@ def test_batch_matches_alone_bit_exact(precision):
         g.close()
 
 
+@pytest.mark.parametrize("persistent", [1, 5, 64])
+def test_persistent_batch_grid(persistent):
+    """A capped (persistent) grid whose blocks loop over the tile work-list of
+    several domains gives the same bits as one block per tile."""
+    from paper_1911_10747_amd import poolboil as pb
+    cases = [pool_case(70, 50, 4, superheat=0.08, seed=1), pool_case(33, 20, 3, superheat=0.25, seed=2)]
+    ref = []
+    for P, d, bc, rho, T in cases:
+        g = gpu_domain(P, bc, rho, T, 1)
+        g.step(24)
+        ref.append(g.read())
+        g.close()
+    doms = [gpu_domain(P, bc, rho, T, 1) for P, d, bc, rho, T in cases]
+    batch = pb.Batch(doms, steps_per_graph=8, persistent_blocks=persistent)
+    batch.step(24)
+    for g, r0 in zip(doms, ref):
+        r = g.read()
+        for k in ("rho", "ux", "uy", "T", "f"):
+            np.testing.assert_array_equal(r[k], r0[k], err_msg=k)
+        g.close()
+    batch.close()
+
+
+def test_checkpoint_resume_fp32_within_tolerance():
+    """FP32-deviation restore re-encodes f(t) against the restored densities:
+    identical to FP32 rounding, so the continued run stays within the FP32 bar."""
+    P, d, bc, rho, T = pool_case(50, 40, 5, superheat=0.2, n_spots=2, seed=4)
+    a = gpu_domain(P, bc, rho, T, 1)
+    a.step(40)
+    s = a.read()
+    a.step(40)
+    ra = a.read()
+    b = gpu_domain(P, bc, rho, T, 1)
+    b.set_state(s["f"], s["T"], 40, a.rho_bar)
+    b.step(40)
+    errs = compare(b.read(), ra)
+    assert all(v <= 2e-5 for v in errs.values()), errs
+    a.close()
+    b.close()
+
+
 def test_nonfinite_flag_is_sticky():
     """A density at the EOS pole region (rho b close to 1) makes the psi
     radicand negative: the step completes and pb_sync reports PB_ENONFINITE."""
