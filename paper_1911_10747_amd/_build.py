@@ -11,6 +11,10 @@ SOURCES = ["pb_kernels.hip", "pb_api.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # multiply-adds are fused only inside one source expression, so a node's
+    # rounding depends on the source alone, not on the code around it (the
+    # specialised and general paths of a kernel give the same bits)
+    "-ffp-contract=on",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),

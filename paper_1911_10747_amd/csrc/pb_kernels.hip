@@ -8,9 +8,10 @@
 //              (Eqs. 11, 14, 15), MRT collision with the improved forcing
 //              (Eqs. 3-7, 9) and the store of f*, rho(t), v(t).
 //   k_thermal  the energy equation (Eq. 24) advanced by RK4 (Eqs. 25-26) with
-//              the isotropic stencils (Eqs. 27-28) over fluid and heater; the
-//              four stages run inside one tile held in LDS with a four-node
-//              halo, so T, rho and v are read from HBM once per step.
+//              the isotropic stencils (Eqs. 27-28) over fluid and heater; one
+//              wavefront sweeps a strip of columns upwards with the four
+//              stages pipelined over consecutive rows in registers, so T, rho
+//              and v are read from HBM once per step (plus the strip halos).
 // plus k_flux (heat flux of Eqs. 36, 38-39, FP64, fixed reduction order),
 // k_init (rest equilibrium) and k_advance (time/parity bookkeeping on device).
 //
@@ -382,8 +383,8 @@ struct Coef9 {
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v) {
     const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
     return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
 __device__ __forceinline__ double from_left(double v) { return dpp_move<0x138>(v); }   // value at x-1
@@ -391,7 +392,10 @@ __device__ __forceinline__ double from_right(double v) { return dpp_move<0x130>(
 
 // harmonic-mean link conductance; a negative value marks the T_top row, whose
 // links take the conductance of the other node
+// (FL: both conductances are fluid ones, positive in any physical state)
+template <bool FL>
 __device__ __forceinline__ double hlink(double a, double b) {
+    if constexpr (FL) return 2.0 * a * b * frcp(a + b);
     if (a < 0.0) return b;
     if (b < 0.0) return a;
     const double s = a + b;
@@ -403,10 +407,22 @@ struct RowIn {
     double T0, lam, rho, vx, vy;
 };
 
-template <typename VT>
+// Thermal row n at column xg.  FL: the row is known to be a fluid row (no
+// wrap, no kind tests).
+template <typename VT, bool FL>
 __device__ __forceinline__ RowIn load_row(cdesc &d, const double PB_GAS *Tin, const double PB_GAS *rho,
                                           const VT PB_GAS *vxg, const VT PB_GAS *vyg, int n, int xg, bool pery) {
     RowIn r{KIND_NONE, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if constexpr (FL) {
+        const uint32_t fi = (uint32_t)(n - d.nys) * (uint32_t)d.pitch + (uint32_t)xg;
+        r.T0 = Tin[(uint32_t)n * (uint32_t)d.pitch + (uint32_t)xg];
+        r.rho = rho[fi];
+        r.lam = d.Cvchi * r.rho;
+        r.vx = vxg[fi];
+        r.vy = vyg[fi];
+        r.kind = KIND_FLUID;
+        return r;
+    }
     int rr = n;
     if (pery) {
         rr %= d.nr;
@@ -433,6 +449,7 @@ __device__ __forceinline__ RowIn load_row(cdesc &d, const double PB_GAS *Tin, co
     return r;
 }
 
+template <bool FL>
 __device__ __forceinline__ double apply9(const Coef9 &c, int kind, double Sc, double SR, double SL, double Nc,
                                          double NR, double NL, double Sc_, double SR_, double SL_) {
     // rows: S* centre row, N* row above, *_ row below; order of Eq. 2
@@ -441,169 +458,159 @@ __device__ __forceinline__ double apply9(const Coef9 &c, int kind, double Sc, do
     const double ra = c.k2 * Nc + c.k5 * NR + c.k6 * NL;
     const double rb = c.k4 * Sc_ + c.k7 * SL_ + c.k8 * SR_;
     double K = rm + (ra + rb);
-    if (kind == KIND_FLUID) K += c.beta * fsqrt(Sc);
+    if (FL || kind == KIND_FLUID) K += c.beta * fsqrt(Sc);
     return K;
 }
 
-// Operator rows of the three previous rows live in LDS (each lane touches only
-// its own column, so no barriers are needed); the row being built stays in
-// registers.  Rows n+1 and n+2 are prefetched from HBM.
-__device__ __forceinline__ void cf_store(double *slot, const Coef9 &c, int lane) {
-    slot[0 * 64 + lane] = c.k0; slot[1 * 64 + lane] = c.k1; slot[2 * 64 + lane] = c.k2;
-    slot[3 * 64 + lane] = c.k3; slot[4 * 64 + lane] = c.k4; slot[5 * 64 + lane] = c.k5;
-    slot[6 * 64 + lane] = c.k6; slot[7 * 64 + lane] = c.k7; slot[8 * 64 + lane] = c.k8;
-    slot[9 * 64 + lane] = c.beta;
-}
-__device__ __forceinline__ Coef9 cf_load(const double *slot, int lane) {
-    Coef9 c;
-    c.k0 = slot[0 * 64 + lane]; c.k1 = slot[1 * 64 + lane]; c.k2 = slot[2 * 64 + lane];
-    c.k3 = slot[3 * 64 + lane]; c.k4 = slot[4 * 64 + lane]; c.k5 = slot[5 * 64 + lane];
-    c.k6 = slot[6 * 64 + lane]; c.k7 = slot[7 * 64 + lane]; c.k8 = slot[8 * 64 + lane];
-    c.beta = slot[9 * 64 + lane];
-    return c;
+// One strip: 64 lanes (56 written columns) by H rows, swept upwards.  The
+// operator rows of the three previous rows stay in registers (the strip is
+// unrolled); rows n+1 and n+2 are prefetched from HBM.  FL: every row the
+// strip reads (H plus four halo rows on each side) is a fluid row, so the
+// kind tests fold away; the arithmetic per node is the same as the general
+// form, so a node gives the same bits in either.
+template <typename VT, int H, int UNR, bool FL>
+__device__ __forceinline__ void thermal_strip(cdesc &d, const PbTile &te, int k, int lane) {
+    const bool pery = !FL && (d.flags & F_PERY) != 0;
+    const int pin = (int)((d.par0 + k) & 1), pout = pin ^ 1;
+    const int64_t t1 = d.t0 + k + 1;
+    const double PB_GAS *Tin = gcast<double>(d.T[pin]);
+    double PB_GAS *Tout = gcast_w<double>(d.T[pout]);
+    const double PB_GAS *rhog = gcast<double>(d.rho[pout]);   // rho(t) written by this step's flow
+    const VT PB_GAS *vxg = gcast<VT>(d.vx);
+    const VT PB_GAS *vyg = gcast<VT>(d.vy);
+    int xg = (te.x0 - 4 + lane) % d.nx;
+    if (xg < 0) xg += d.nx;
+    const bool out_lane = lane >= 4 && lane < 60 && (te.x0 + lane - 4) < d.nx;
+    const double c1_solid = 1.0 / (d.rho_S * d.C_S);
+    const double lat_a = d.kappa / d.Tc, lat_b = (1.0 + d.kappa) * d.inv_sqrtTc;
+    const double W1 = 6.0 / 9.0, W2 = 6.0 / 36.0, A1 = 3.0 / 9.0, A2 = 3.0 / 36.0;
+
+    // carried state; "_1" = row n-1, "_2" = row n-2 and so on
+    int kind_1 = KIND_NONE;
+    double lam_1 = 0.0, lamR_1 = 0.0, rho_1 = 0.0;
+    double vx_1 = 0.0, vy_1 = 0.0, vy_2 = 0.0;
+    double p_1 = 0.0, m_1 = 0.0, p_2 = 0.0, m_2 = 0.0;   // vx + vy and vx - vy
+    double lN_2 = 0.0, lNEL_2 = 0.0, lNWR_2 = 0.0;       // links of row n-2 seen from row n-1
+    double T0_1 = 0.0, T0_2 = 0.0, T0_3 = 0.0, T0_4 = 0.0;
+    double T0L_1 = 0.0, T0R_1 = 0.0, T0L_2 = 0.0, T0R_2 = 0.0;
+    double s1_2 = 0.0, s1L_2 = 0.0, s1R_2 = 0.0, s1_3 = 0.0, s1L_3 = 0.0, s1R_3 = 0.0;
+    double s2_3 = 0.0, s2L_3 = 0.0, s2R_3 = 0.0, s2_4 = 0.0, s2L_4 = 0.0, s2R_4 = 0.0;
+    double s3_4 = 0.0, s3L_4 = 0.0, s3R_4 = 0.0, s3_5 = 0.0, s3L_5 = 0.0, s3R_5 = 0.0;
+    double acc_2 = 0.0, acc_3 = 0.0, acc_4 = 0.0;
+    int kd_2 = KIND_NONE, kd_3 = KIND_NONE, kd_4 = KIND_NONE;
+    Coef9 cf_2{}, cf_3{}, cf_4{};
+    bool bad = false;
+
+    const int nbeg = te.y0 - 4, nend = te.y0 + H + 3;
+    RowIn nx1 = load_row<VT, FL>(d, Tin, rhog, vxg, vyg, nbeg, xg, pery);
+    RowIn nx2 = load_row<VT, FL>(d, Tin, rhog, vxg, vyg, nbeg + 1, xg, pery);
+#pragma unroll UNR
+    for (int j = 0; j < H + 8; ++j) {
+        const int n = nbeg + j;
+        const RowIn cur = nx1;
+        nx1 = nx2;
+        if (n + 2 <= nend) nx2 = load_row<VT, FL>(d, Tin, rhog, vxg, vyg, n + 2, xg, pery);
+
+        // new row n: neighbours across lanes
+        const double lamL = from_left(cur.lam), lamR = from_right(cur.lam);
+        const double T0L = from_left(cur.T0), T0R = from_right(cur.T0);
+        const double p = cur.vx + cur.vy, m = cur.vx - cur.vy;
+
+        // operator of row a = n-1
+        const double lE = hlink<FL>(lam_1, lamR_1), lN = hlink<FL>(lam_1, cur.lam);
+        const double lNE = hlink<FL>(lam_1, lamR), lNW = hlink<FL>(lam_1, lamL);
+        const double lW = from_left(lE);
+        // Eq. 27 on v (v = 0 outside the fluid): 3 sum_i w_i e_i . v(x + e_i),
+        // grouped as U(x+1) - V(x-1) + (vy(above) - vy(below)) / 9
+        const double U = (1.0 / 9.0) * vx_1 + (1.0 / 36.0) * (p + m_2);
+        const double V = (1.0 / 9.0) * vx_1 + (1.0 / 36.0) * (m + p_2);
+        const double UR = from_right(U), VL = from_left(V);
+        Coef9 cf{};
+        if (FL || kind_1 == KIND_FLUID || kind_1 == KIND_SOLID) {
+            double C1;
+            if (FL || kind_1 == KIND_FLUID) C1 = frcp(rho_1 * d.Cv); else C1 = c1_solid;
+            const double c1 = W1 * C1 * lE, c2 = W1 * C1 * lN, c3 = W1 * C1 * lW, c4 = W1 * C1 * lN_2;
+            const double c5 = W2 * C1 * lNE, c6 = W2 * C1 * lNW, c7 = W2 * C1 * lNEL_2, c8 = W2 * C1 * lNWR_2;
+            cf.k0 = -(((c1 + c2) + (c3 + c4)) + ((c5 + c6) + (c7 + c8)));
+            cf.k1 = c1; cf.k2 = c2; cf.k3 = c3; cf.k4 = c4;
+            cf.k5 = c5; cf.k6 = c6; cf.k7 = c7; cf.k8 = c8;
+            if (FL || kind_1 == KIND_FLUID) {
+                const double divv = 3.0 * ((UR - VL) + (1.0 / 9.0) * (cur.vy - vy_2));
+                const double br = d.b * rho_1;
+                const double A = rho_1 * d.R * frcp(1.0 - br);
+                const double B = d.a * d.kappa * rho_1 * rho_1 * frcp(1.0 + 2.0 * br - br * br);
+                const double AL = -C1 * divv * A, BE = -C1 * divv * B;
+                cf.k0 += AL - BE * lat_a;
+                cf.beta = BE * lat_b;
+                // advection -v.grad T with Eq. 27
+                cf.k1 -= A1 * vx_1;  cf.k3 += A1 * vx_1;
+                cf.k2 -= A1 * vy_1;  cf.k4 += A1 * vy_1;
+                cf.k5 -= A2 * p_1;  cf.k7 += A2 * p_1;
+                cf.k6 += A2 * m_1;  cf.k8 -= A2 * m_1;
+            }
+        }
+
+        // stage 1 on row n-1 (input T0 rows n-2, n-1, n)
+        const double K1 = apply9<FL>(cf, kind_1, T0_1, T0R_1, T0L_1, cur.T0, T0R, T0L, T0_2, T0R_2, T0L_2);
+        const double s1 = T0_1 + 0.5 * K1;
+        const double acc1 = K1;
+        const double s1L = from_left(s1), s1R = from_right(s1);
+        // stage 2 on row n-2 (input s1 rows n-3, n-2, n-1)
+        const double K2 = apply9<FL>(cf_2, kd_2, s1_2, s1R_2, s1L_2, s1, s1R, s1L, s1_3, s1R_3, s1L_3);
+        const double s2 = T0_2 + 0.5 * K2;
+        const double acc2 = acc_2 + 2.0 * K2;
+        const double s2L = from_left(s2), s2R = from_right(s2);
+        // stage 3 on row n-3 (input s2 rows n-4, n-3, n-2)
+        const double K3 = apply9<FL>(cf_3, kd_3, s2_3, s2R_3, s2L_3, s2, s2R, s2L, s2_4, s2R_4, s2L_4);
+        const double s3 = T0_3 + K3;
+        const double acc3 = acc_3 + 2.0 * K3;
+        const double s3L = from_left(s3), s3R = from_right(s3);
+        // stage 4 and the update on row e = n-4 (input s3 rows n-5, n-4, n-3)
+        const double K4 = apply9<FL>(cf_4, kd_4, s3_4, s3R_4, s3L_4, s3, s3R, s3L, s3_5, s3R_5, s3L_5);
+        const int e = n - 4;
+        if (out_lane && e >= te.y0 && e < te.y0 + H && e >= 0 && e < d.nr) {
+            double Tn;
+            if (!FL && kd_4 == KIND_FIXED) {
+                Tn = (t1 >= d.alt_t0 && t1 < d.alt_t1) ? gcast<double>(d.Tb_alt)[xg]
+                                                       : gcast<double>(d.Tb)[xg];   // T_b(x, t+1)
+            } else {
+                Tn = T0_4 + (1.0 / 6.0) * (acc_4 + K4);
+            }
+            Tout[(uint32_t)e * (uint32_t)d.pitch + (uint32_t)xg] = Tn;
+            bad = bad || !(Tn - Tn == 0.0);
+        }
+
+        // shift the windows by one row
+        cf_4 = cf_3; cf_3 = cf_2; cf_2 = cf;
+        s3_5 = s3_4; s3L_5 = s3L_4; s3R_5 = s3R_4;
+        s3_4 = s3; s3L_4 = s3L; s3R_4 = s3R;
+        s2_4 = s2_3; s2L_4 = s2L_3; s2R_4 = s2R_3;
+        s2_3 = s2; s2L_3 = s2L; s2R_3 = s2R;
+        s1_3 = s1_2; s1L_3 = s1L_2; s1R_3 = s1R_2;
+        s1_2 = s1; s1L_2 = s1L; s1R_2 = s1R;
+        acc_4 = acc3; acc_3 = acc2; acc_2 = acc1;
+        kd_4 = kd_3; kd_3 = kd_2; kd_2 = kind_1;
+        T0_4 = T0_3; T0_3 = T0_2;
+        T0_2 = T0_1; T0L_2 = T0L_1; T0R_2 = T0R_1;
+        T0_1 = cur.T0; T0L_1 = T0L; T0R_1 = T0R;
+        lN_2 = lN; lNEL_2 = from_left(lNE); lNWR_2 = from_right(lNW);
+        vy_2 = vy_1; p_2 = p_1; m_2 = m_1;
+        vx_1 = cur.vx; vy_1 = cur.vy; p_1 = p; m_1 = m;
+        lam_1 = cur.lam; lamR_1 = lamR; rho_1 = cur.rho; kind_1 = cur.kind;
+    }
+    if (bad) flag_error(d);
 }
 
 template <typename VT, int H, int WPE, int UNR>
 __global__ __launch_bounds__(64, WPE) void k_thermal_sweep(const PbDesc *const *__restrict__ dps,
                                                             const PbTile *__restrict__ tiles, int ntiles, int k) {
-    __shared__ double s_cf[3][10 * 64];
     const int lane = threadIdx.x;
     for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
         const PbTile te = tiles[tl];
         cdesc &d = *(const PbDesc PB_CAS *)dps[te.dom];
-        const bool pery = (d.flags & F_PERY) != 0;
-        const int pin = (int)((d.par0 + k) & 1), pout = pin ^ 1;
-        const int64_t t1 = d.t0 + k + 1;
-        const double PB_GAS *Tin = gcast<double>(d.T[pin]);
-        double PB_GAS *Tout = gcast_w<double>(d.T[pout]);
-        const double PB_GAS *rhog = gcast<double>(d.rho[pout]);   // rho(t) written by this step's flow
-        const VT PB_GAS *vxg = gcast<VT>(d.vx);
-        const VT PB_GAS *vyg = gcast<VT>(d.vy);
-        int xg = (te.x0 - 4 + lane) % d.nx;
-        if (xg < 0) xg += d.nx;
-        const bool out_lane = lane >= 4 && lane < 60 && (te.x0 + lane - 4) < d.nx;
-        const double c1_solid = 1.0 / (d.rho_S * d.C_S);
-        const double lat_a = d.kappa / d.Tc, lat_b = (1.0 + d.kappa) * d.inv_sqrtTc;
-        const double W1 = 6.0 / 9.0, W2 = 6.0 / 36.0, A1 = 3.0 / 9.0, A2 = 3.0 / 36.0;
-
-        // carried state; "_1" = row n-1, "_2" = row n-2 and so on
-        int kind_1 = KIND_NONE;
-        double lam_1 = 0.0, lamR_1 = 0.0, rho_1 = 0.0;
-        double vx_1 = 0.0, vy_1 = 0.0, vxL_1 = 0.0, vxR_1 = 0.0, vyL_1 = 0.0, vyR_1 = 0.0;
-        double vxL_2 = 0.0, vxR_2 = 0.0, vyL_2 = 0.0, vyR_2 = 0.0, vy_2 = 0.0;
-        double lN_2 = 0.0, lNEL_2 = 0.0, lNWR_2 = 0.0;      // links of row n-2 seen from row n-1
-        double T0_1 = 0.0, T0_2 = 0.0, T0_3 = 0.0, T0_4 = 0.0;
-        double T0L_1 = 0.0, T0R_1 = 0.0, T0L_2 = 0.0, T0R_2 = 0.0;
-        double s1_2 = 0.0, s1L_2 = 0.0, s1R_2 = 0.0, s1_3 = 0.0, s1L_3 = 0.0, s1R_3 = 0.0;
-        double s2_3 = 0.0, s2L_3 = 0.0, s2R_3 = 0.0, s2_4 = 0.0, s2L_4 = 0.0, s2R_4 = 0.0;
-        double s3_4 = 0.0, s3L_4 = 0.0, s3R_4 = 0.0, s3_5 = 0.0, s3L_5 = 0.0, s3R_5 = 0.0;
-        double acc_2 = 0.0, acc_3 = 0.0, acc_4 = 0.0;
-        int kd_2 = KIND_NONE, kd_3 = KIND_NONE, kd_4 = KIND_NONE;
-        bool bad = false;
-        {
-            const Coef9 z{};
-            for (int q = 0; q < 3; ++q) cf_store(s_cf[q], z, lane);
-        }
-
-        const int nbeg = te.y0 - 4, nend = te.y0 + H + 3;
-        RowIn nx1 = load_row<VT>(d, Tin, rhog, vxg, vyg, nbeg, xg, pery);
-        RowIn nx2 = load_row<VT>(d, Tin, rhog, vxg, vyg, nbeg + 1, xg, pery);
-#pragma unroll UNR
-        for (int j = 0; j < H + 8; ++j) {
-            const int n = nbeg + j;
-            const RowIn cur = nx1;
-            nx1 = nx2;
-            if (n + 2 <= nend) nx2 = load_row<VT>(d, Tin, rhog, vxg, vyg, n + 2, xg, pery);
-            double *slot_2 = s_cf[(j + 1) % 3];     // operator of row n-2
-            double *slot_3 = s_cf[j % 3];           // operator of row n-3
-            double *slot_4 = s_cf[(j + 2) % 3];     // operator of row n-4; then reused for row n-1
-
-            // new row n: neighbours across lanes
-            const double lamL = from_left(cur.lam), lamR = from_right(cur.lam);
-            const double vxL = from_left(cur.vx), vxR = from_right(cur.vx);
-            const double vyL = from_left(cur.vy), vyR = from_right(cur.vy);
-            const double T0L = from_left(cur.T0), T0R = from_right(cur.T0);
-
-            // operator of row a = n-1
-            const double lE = hlink(lam_1, lamR_1), lN = hlink(lam_1, cur.lam);
-            const double lNE = hlink(lam_1, lamR), lNW = hlink(lam_1, lamL);
-            const double lW = from_left(lE);
-            Coef9 cf{};
-            if (kind_1 == KIND_FLUID || kind_1 == KIND_SOLID) {
-                double C1;
-                if (kind_1 == KIND_FLUID) C1 = frcp(rho_1 * d.Cv); else C1 = c1_solid;
-                const double c1 = W1 * C1 * lE, c2 = W1 * C1 * lN, c3 = W1 * C1 * lW, c4 = W1 * C1 * lN_2;
-                const double c5 = W2 * C1 * lNE, c6 = W2 * C1 * lNW, c7 = W2 * C1 * lNEL_2, c8 = W2 * C1 * lNWR_2;
-                cf.k0 = -(((c1 + c2) + (c3 + c4)) + ((c5 + c6) + (c7 + c8)));
-                cf.k1 = c1; cf.k2 = c2; cf.k3 = c3; cf.k4 = c4;
-                cf.k5 = c5; cf.k6 = c6; cf.k7 = c7; cf.k8 = c8;
-                if (kind_1 == KIND_FLUID) {
-                    // Eq. 27 on v (v = 0 outside the fluid)
-                    const double divv = 3.0 * ((1.0 / 9.0) * (vxR_1 - vxL_1 + cur.vy - vy_2) +
-                                               (1.0 / 36.0) * (vxR - vxL - vxL_2 + vxR_2 + vyR + vyL - vyL_2 - vyR_2));
-                    const double br = d.b * rho_1;
-                    const double A = rho_1 * d.R * frcp(1.0 - br);
-                    const double B = d.a * d.kappa * rho_1 * rho_1 * frcp(1.0 + 2.0 * br - br * br);
-                    const double AL = -C1 * divv * A, BE = -C1 * divv * B;
-                    cf.k0 += AL - BE * lat_a;
-                    cf.beta = BE * lat_b;
-                    // advection -v.grad T with Eq. 27
-                    cf.k1 -= A1 * vx_1;  cf.k3 += A1 * vx_1;
-                    cf.k2 -= A1 * vy_1;  cf.k4 += A1 * vy_1;
-                    cf.k5 -= A2 * (vx_1 + vy_1);  cf.k7 += A2 * (vx_1 + vy_1);
-                    cf.k6 -= A2 * (vy_1 - vx_1);  cf.k8 += A2 * (vy_1 - vx_1);
-                }
-            }
-
-            // stage 1 on row n-1 (input T0 rows n-2, n-1, n)
-            const double K1 = apply9(cf, kind_1, T0_1, T0R_1, T0L_1, cur.T0, T0R, T0L, T0_2, T0R_2, T0L_2);
-            const double s1 = T0_1 + 0.5 * K1;
-            const double acc1 = K1;
-            const double s1L = from_left(s1), s1R = from_right(s1);
-            // stage 2 on row n-2 (input s1 rows n-3, n-2, n-1)
-            const double K2 = apply9(cf_load(slot_2, lane), kd_2, s1_2, s1R_2, s1L_2, s1, s1R, s1L, s1_3, s1R_3, s1L_3);
-            const double s2 = T0_2 + 0.5 * K2;
-            const double acc2 = acc_2 + 2.0 * K2;
-            const double s2L = from_left(s2), s2R = from_right(s2);
-            // stage 3 on row n-3 (input s2 rows n-4, n-3, n-2)
-            const double K3 = apply9(cf_load(slot_3, lane), kd_3, s2_3, s2R_3, s2L_3, s2, s2R, s2L, s2_4, s2R_4, s2L_4);
-            const double s3 = T0_3 + K3;
-            const double acc3 = acc_3 + 2.0 * K3;
-            const double s3L = from_left(s3), s3R = from_right(s3);
-            // stage 4 and the update on row e = n-4 (input s3 rows n-5, n-4, n-3)
-            const double K4 = apply9(cf_load(slot_4, lane), kd_4, s3_4, s3R_4, s3L_4, s3, s3R, s3L, s3_5, s3R_5, s3L_5);
-            const int e = n - 4;
-            if (out_lane && e >= te.y0 && e < te.y0 + H && e >= 0 && e < d.nr) {
-                double Tn;
-                if (kd_4 == KIND_FIXED) {
-                    Tn = (t1 >= d.alt_t0 && t1 < d.alt_t1) ? gcast<double>(d.Tb_alt)[xg]
-                                                           : gcast<double>(d.Tb)[xg];   // T_b(x, t+1)
-                } else {
-                    Tn = T0_4 + (1.0 / 6.0) * (acc_4 + K4);
-                }
-                Tout[(uint32_t)e * (uint32_t)d.pitch + (uint32_t)xg] = Tn;
-                bad = bad || !(Tn - Tn == 0.0);
-            }
-            cf_store(slot_4, cf, lane);             // row n-1 takes the slot of row n-4
-
-            // shift the windows by one row
-            s3_5 = s3_4; s3L_5 = s3L_4; s3R_5 = s3R_4;
-            s3_4 = s3; s3L_4 = s3L; s3R_4 = s3R;
-            s2_4 = s2_3; s2L_4 = s2L_3; s2R_4 = s2R_3;
-            s2_3 = s2; s2L_3 = s2L; s2R_3 = s2R;
-            s1_3 = s1_2; s1L_3 = s1L_2; s1R_3 = s1R_2;
-            s1_2 = s1; s1L_2 = s1L; s1R_2 = s1R;
-            acc_4 = acc3; acc_3 = acc2; acc_2 = acc1;
-            kd_4 = kd_3; kd_3 = kd_2; kd_2 = kind_1;
-            T0_4 = T0_3; T0_3 = T0_2;
-            T0_2 = T0_1; T0L_2 = T0L_1; T0R_2 = T0R_1;
-            T0_1 = cur.T0; T0L_1 = T0L; T0R_1 = T0R;
-            lN_2 = lN; lNEL_2 = from_left(lNE); lNWR_2 = from_right(lNW);
-            vxL_2 = vxL_1; vxR_2 = vxR_1; vyL_2 = vyL_1; vyR_2 = vyR_1; vy_2 = vy_1;
-            vx_1 = cur.vx; vy_1 = cur.vy; vxL_1 = vxL; vxR_1 = vxR; vyL_1 = vyL; vyR_1 = vyR;
-            lam_1 = cur.lam; lamR_1 = lamR; rho_1 = cur.rho; kind_1 = cur.kind;
-        }
-        if (bad) flag_error(d);
+        const bool fl = !(d.flags & F_PERY) && te.y0 - 4 >= d.nys && te.y0 + H + 3 < d.nr;
+        if (fl) thermal_strip<VT, H, UNR, true>(d, te, k, lane);
+        else thermal_strip<VT, H, UNR, false>(d, te, k, lane);
     }
 }
 
