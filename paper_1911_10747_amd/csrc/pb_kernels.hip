@@ -134,21 +134,22 @@ __device__ __forceinline__ void pull_inner(const FT PB_GAS *fin, const double PB
     }
 }
 
-// Same, with the reference densities of the FP32 decode taken from an LDS
-// copy of rho(t-1) over the tile plus two rings (row stride RW, node at (lx, ly)
-// of that copy).
-template <typename FT, int RW>
-__device__ __forceinline__ void pull_inner_lds(const FT PB_GAS *fin, const double *s_rho, uint32_t plane,
-                                               uint32_t pitch, uint32_t idx, int lx, int ly, double f[9]) {
+// Same pull split in two for FP32 storage, with the reference densities of
+// the decode taken from an LDS copy of rho(t-1) over the tile plus two rings
+// (row stride RW, node at (lx, ly) of that copy), so that the loads of a tile
+// can be in flight before that copy is complete.
+__device__ __forceinline__ void load_inner_raw(const float PB_GAS *fin, uint32_t plane, uint32_t pitch, uint32_t idx,
+                                               float v[9]) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const uint32_t src = idx - (uint32_t)(kEY[i] * (int)pitch) - (uint32_t)kEX[i];
-        const FT v = (fin + (uint32_t)i * plane)[src];
-        if constexpr (std::is_same<FT, float>::value)
-            f[i] = kW[i] * s_rho[(ly - kEY[i]) * RW + lx - kEX[i]] + (double)v;
-        else
-            f[i] = v;
+        v[i] = (fin + (uint32_t)i * plane)[src];
     }
+}
+template <int RW>
+__device__ __forceinline__ void decode_lds(const double *s_rho, int lx, int ly, const float v[9], double f[9]) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = kW[i] * s_rho[(ly - kEY[i]) * RW + lx - kEX[i]] + (double)v[i];
 }
 
 template <typename FT>
@@ -181,14 +182,6 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
     const uint32_t pitch = (uint32_t)d.pitch, plane = (uint32_t)d.nyf * pitch;
     const uint32_t toff = (uint32_t)d.nys * pitch;           // fluid row 0 in the T array
     bool bad = false;
-    if constexpr (RLDS) {
-        // all these nodes lie inside the fluid (the tile is two nodes from every edge)
-        for (int q = threadIdx.x; q < RW * RH; q += BX * BY) {
-            const int qx = q % RW, qy = q / RW;
-            s_rho[q] = rin[(uint32_t)(te.y0 - 2 + qy) * pitch + (uint32_t)(te.x0 - 2 + qx)];
-        }
-        __syncthreads();
-    }
 
     // this thread's node; positions past the edge wrap once so that the first
     // column/row beyond holds the periodic neighbour
@@ -199,49 +192,100 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
     const bool live = INNER || (xw < d.nx && yw < d.nyf);
     double f[9], rho = 0.0, jx = 0.0, jy = 0.0, psi = 0.0;
     const uint32_t idx = (uint32_t)yw * pitch + (uint32_t)xw;
-    if (live) {
-        if constexpr (RLDS) pull_inner_lds<FT, RW>(fin, s_rho, plane, pitch, idx, tx + 2, ty + 2, f);
-        else if (INNER) pull_inner<FT>(fin, rin, plane, pitch, idx, f);
-        else pull_node<FT>(d, fin, rin, xw, yw, pery, f);
+
+    // ring node of psi around the tile handled by this thread, if any
+    const bool has_h = (int)threadIdx.x < NHALO;
+    int lx = 0, ly = 0;
+    {
+        const int h = threadIdx.x;
+        if (h < LW) { lx = h; ly = 0; }
+        else if (h < 2 * LW) { lx = h - LW; ly = LH - 1; }
+        else if (h < 2 * LW + BY) { lx = 0; ly = h - 2 * LW + 1; }
+        else { lx = LW - 1; ly = h - 2 * LW - BY + 1; }
+    }
+
+    if constexpr (RLDS) {
+        // Every load of the tile is issued before the first wait: the rho(t-1)
+        // copy (tile plus two rings, all inside the fluid since the tile is two
+        // nodes from every edge), then the populations and T of this thread's
+        // node and of its ring node.
+        constexpr int NQ = (RW * RH + BX * BY - 1) / (BX * BY);
+        double rq[NQ];
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+            const int q = threadIdx.x + u * BX * BY;
+            if (q < RW * RH) {
+                const int qx = q % RW, qy = q / RW;
+                rq[u] = rin[(uint32_t)(te.y0 - 2 + qy) * pitch + (uint32_t)(te.x0 - 2 + qx)];
+            }
+        }
+        float v[9], vh[9];
+        load_inner_raw(fin, plane, pitch, idx, v);
+        const double Tn = Tt[toff + idx];
+        const uint32_t hidx = (uint32_t)(te.y0 + ly - 1) * pitch + (uint32_t)(te.x0 + lx - 1);
+        double Th = 0.0;
+        if (has_h) {
+            load_inner_raw(fin, plane, pitch, hidx, vh);
+            Th = Tt[toff + hidx];
+        }
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+            const int q = threadIdx.x + u * BX * BY;
+            if (q < RW * RH) s_rho[q] = rq[u];
+        }
+        __syncthreads();
+        decode_lds<RW>(s_rho, tx + 2, ty + 2, v, f);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             rho += f[i];
             jx += kEX[i] * f[i];
             jy += kEY[i] * f[i];
         }
-        psi = eos_psi(d, rho, Tt[toff + idx], bad);
-    }
-    s_psi[(ty + 1) * LW + tx + 1] = psi;
-
-    // ring of psi around the tile
-    if ((int)threadIdx.x < NHALO) {
-        const int h = threadIdx.x;
-        int lx, ly;
-        if (h < LW) { lx = h; ly = 0; }
-        else if (h < 2 * LW) { lx = h - LW; ly = LH - 1; }
-        else if (h < 2 * LW + BY) { lx = 0; ly = h - 2 * LW + 1; }
-        else { lx = LW - 1; ly = h - 2 * LW - BY + 1; }
-        int xh = te.x0 + lx - 1, yh = te.y0 + ly - 1;
-        bool ok = true;
-        if (!INNER) {
-            xh = wrap_once(xh, d.nx);
-            ok = xh >= 0 && xh < d.nx;
-            if (pery) yh = wrap_once(yh, d.nyf);
-            ok = ok && yh >= 0 && yh < d.nyf;
-        }
-        double ph = 0.0;
-        if (ok) {
+        psi = eos_psi(d, rho, Tn, bad);
+        s_psi[(ty + 1) * LW + tx + 1] = psi;
+        if (has_h) {
             double fh[9], rh = 0.0;
-            const uint32_t hidx = (uint32_t)yh * pitch + (uint32_t)xh;
-            if constexpr (RLDS) pull_inner_lds<FT, RW>(fin, s_rho, plane, pitch, hidx, lx + 1, ly + 1, fh);
-            else if (INNER) pull_inner<FT>(fin, rin, plane, pitch, hidx, fh);
-            else pull_node<FT>(d, fin, rin, xh, yh, pery, fh);
+            decode_lds<RW>(s_rho, lx + 1, ly + 1, vh, fh);
 #pragma unroll
             for (int i = 0; i < 9; ++i) rh += fh[i];
             bool dummy = false;  // errors are flagged by the owning tile
-            ph = eos_psi(d, rh, Tt[toff + hidx], dummy);
+            s_psi[ly * LW + lx] = eos_psi(d, rh, Th, dummy);
         }
-        s_psi[ly * LW + lx] = ph;
+    } else {
+        if (live) {
+            if (INNER) pull_inner<FT>(fin, rin, plane, pitch, idx, f);
+            else pull_node<FT>(d, fin, rin, xw, yw, pery, f);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                rho += f[i];
+                jx += kEX[i] * f[i];
+                jy += kEY[i] * f[i];
+            }
+            psi = eos_psi(d, rho, Tt[toff + idx], bad);
+        }
+        s_psi[(ty + 1) * LW + tx + 1] = psi;
+        if (has_h) {
+            int xh = te.x0 + lx - 1, yh = te.y0 + ly - 1;
+            bool ok = true;
+            if (!INNER) {
+                xh = wrap_once(xh, d.nx);
+                ok = xh >= 0 && xh < d.nx;
+                if (pery) yh = wrap_once(yh, d.nyf);
+                ok = ok && yh >= 0 && yh < d.nyf;
+            }
+            double ph = 0.0;
+            if (ok) {
+                double fh[9], rh = 0.0;
+                const uint32_t hidx = (uint32_t)yh * pitch + (uint32_t)xh;
+                if (INNER) pull_inner<FT>(fin, rin, plane, pitch, hidx, fh);
+                else pull_node<FT>(d, fin, rin, xh, yh, pery, fh);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) rh += fh[i];
+                bool dummy = false;  // errors are flagged by the owning tile
+                ph = eos_psi(d, rh, Tt[toff + hidx], dummy);
+            }
+            s_psi[ly * LW + lx] = ph;
+        }
     }
     __syncthreads();
 
