@@ -161,6 +161,129 @@ __device__ __forceinline__ void store_pop(FT PB_GAS *fout, uint32_t plane, uint3
         (fout + (uint32_t)i * plane)[idx] = fs;
 }
 
+// Lane exchange with DPP wave shifts (a VALU move, no LDS round trip): wave_shr:1
+// gives lane i the value of lane i-1 (column x-1), wave_shl:1 that of lane i+1.
+// The end lanes receive 0; they are halo columns whose results are discarded.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double from_left(double v) { return dpp_move<0x138>(v); }   // value at x-1
+__device__ __forceinline__ double from_right(double v) { return dpp_move<0x130>(v); }  // value at x+1
+
+// ------------------------------------------------------------ node update
+// rho and momentum of the pulled populations (Eq. 10 without the force)
+__device__ __forceinline__ void node_moments(const double f[9], double &rho, double &jx, double &jy) {
+    rho = 0.0;
+    jx = 0.0;
+    jy = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        rho += f[i];
+        jx += kEX[i] * f[i];
+        jy += kEY[i] * f[i];
+    }
+}
+
+// Forces, velocity and collision of one fluid node from its pulled
+// populations f, rho, j, its psi and, for i = 1..8, psi of the neighbour
+// x + e_i (pn[i]) or, where bit i of wmask marks that neighbour as a wall,
+// the wall's adhesion gamma (gw[i]).  Writes f*, rho(t), v(t) at oidx (or, in
+// read mode, the pulled state).  Returns true if the node is not finite.
+// Every flow kernel updates its nodes through this one function, so a node
+// gives the same bits whatever the launch shape.
+template <typename FT, int MODE>
+__device__ __forceinline__ bool node_update(cdesc &d, const double f[9], double rho, double jx, double jy,
+                                            double psi, const double pn[9], const double gw[9], uint32_t wmask,
+                                            uint32_t oidx, int pout) {
+    const bool frozen = (d.flags & F_FROZEN) != 0;
+    const uint32_t plane = (uint32_t)d.nyf * (uint32_t)d.pitch;
+    // Eq. 11 over fluid neighbours, Eq. 14 over wall neighbours
+    double sfx = 0.0, sfy = 0.0, sax = 0.0, say = 0.0;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        if (!((wmask >> i) & 1u)) {
+            sfx += kWF[i] * kEX[i] * pn[i];
+            sfy += kWF[i] * kEY[i] * pn[i];
+        } else {
+            sax += kWF[i] * kEX[i] * gw[i];
+            say += kWF[i] * kEY[i] * gw[i];
+        }
+    }
+    const double Fmx = -d.G * psi * sfx, Fmy = -d.G * psi * sfy;
+    const double Fax = -psi * sax, Fay = -psi * say;
+    const double Fx = Fmx + Fax;
+    const double Fy = Fmy + Fay - (rho - d.rho_bar) * d.g;       // Eq. 15
+    const double inv_rho = frcp(rho);
+    double vx = (jx + 0.5 * Fx) * inv_rho;                         // Eq. 10
+    double vy = (jy + 0.5 * Fy) * inv_rho;
+    if (frozen) { vx = 0.0; vy = 0.0; }
+
+    if constexpr (MODE == PB_MODE_READ) {
+        double PB_GAS *rdf = gcast_w<double>(d.rd_f);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) (rdf + (uint32_t)i * plane)[oidx] = f[i];
+        gcast_w<double>(d.rd_rho)[oidx] = rho;
+        gcast_w<double>(d.rd_vx)[oidx] = vx;
+        gcast_w<double>(d.rd_vy)[oidx] = vy;
+    } else {
+        // moments m = M f (Eq. 6)
+        const double sa = f[1] + f[2] + f[3] + f[4];
+        const double sd = f[5] + f[6] + f[7] + f[8];
+        const double m1 = -4.0 * f[0] - sa + 2.0 * sd;
+        const double m2 = 4.0 * f[0] - 2.0 * sa + sd;
+        const double m4 = -2.0 * f[1] + 2.0 * f[3] + f[5] - f[6] - f[7] + f[8];
+        const double m6 = -2.0 * f[2] + 2.0 * f[4] + f[5] + f[6] - f[7] - f[8];
+        const double m7 = f[1] - f[2] + f[3] - f[4];
+        const double m8 = f[5] - f[6] + f[7] - f[8];
+        // equilibria (Eq. 6) with u = v of Eq. 10
+        const double u2 = vx * vx + vy * vy;
+        const double meq1 = rho * (-2.0 + 3.0 * u2), meq2 = rho * (1.0 - 3.0 * u2);
+        const double meq4 = -rho * vx, meq6 = -rho * vy;
+        const double meq7 = rho * (vx * vx - vy * vy), meq8 = rho * vx * vy;
+        // forcing of Eq. 9; the varpi term times (1 - s_e/2) equals
+        // 12 varpi s_e |F|^2 / psi^2 because tau_e = 1/s_e
+        const double Fwx = (d.flags & F_FMONLY) ? Fmx : Fmx + Fax;
+        const double Fwy = (d.flags & F_FMONLY) ? Fmy : Fmy + Fay;
+        const double uF = vx * Fx + vy * Fy;
+        const double cw = 12.0 * d.varpi * d.s_e * (Fwx * Fwx + Fwy * Fwy) * frcp(psi * psi);
+        const double cw2 = (d.flags & F_S2PLUS) ? cw : -cw;
+        const double se = d.s_e, sq = d.s_q;
+        const double snu = frcp(d.tau_V + (rho - d.rho_V) * d.ktau);   // Eq. 5
+        const double ms1 = m1 - se * (m1 - meq1) + (1.0 - 0.5 * se) * (6.0 * uF) + cw;
+        const double ms2 = m2 - se * (m2 - meq2) + (1.0 - 0.5 * se) * (-6.0 * uF) + cw2;
+        const double ms3 = jx + Fx;                       // s_j drops out (Eq. 7 + Eq. 10)
+        const double ms4 = m4 - sq * (m4 - meq4) + (1.0 - 0.5 * sq) * (-Fx);
+        const double ms5 = jy + Fy;
+        const double ms6 = m6 - sq * (m6 - meq6) + (1.0 - 0.5 * sq) * (-Fy);
+        const double ms7 = m7 - snu * (m7 - meq7) + (1.0 - 0.5 * snu) * (2.0 * (vx * Fx - vy * Fy));
+        const double ms8 = m8 - snu * (m8 - meq8) + (1.0 - 0.5 * snu) * (vx * Fy + vy * Fx);
+        // f* = M^{-1} m*, M^{-1} = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
+        const double a0 = rho * (1.0 / 9.0), a1 = ms1 * (1.0 / 36.0), a2 = ms2 * (1.0 / 36.0);
+        const double a3 = ms3 * (1.0 / 6.0), a4 = ms4 * (1.0 / 12.0), a5 = ms5 * (1.0 / 6.0);
+        const double a6 = ms6 * (1.0 / 12.0), a7 = ms7 * 0.25, a8 = ms8 * 0.25;
+        const double c0 = a0 - a1 - 2.0 * a2;       // axis-common part
+        const double cd = a0 + 2.0 * a1 + a2;       // diagonal-common part
+        FT PB_GAS *fout = gcast_w<FT>(d.f[pout]);
+        store_pop<FT>(fout, plane, oidx, 0, a0 - 4.0 * a1 + 4.0 * a2, rho);
+        store_pop<FT>(fout, plane, oidx, 1, c0 + a3 - 2.0 * a4 + a7, rho);
+        store_pop<FT>(fout, plane, oidx, 2, c0 + a5 - 2.0 * a6 - a7, rho);
+        store_pop<FT>(fout, plane, oidx, 3, c0 - a3 + 2.0 * a4 + a7, rho);
+        store_pop<FT>(fout, plane, oidx, 4, c0 - a5 + 2.0 * a6 - a7, rho);
+        store_pop<FT>(fout, plane, oidx, 5, cd + a3 + a4 + a5 + a6 + a8, rho);
+        store_pop<FT>(fout, plane, oidx, 6, cd - a3 - a4 + a5 + a6 - a8, rho);
+        store_pop<FT>(fout, plane, oidx, 7, cd - a3 - a4 - a5 - a6 + a8, rho);
+        store_pop<FT>(fout, plane, oidx, 8, cd + a3 + a4 - a5 - a6 - a8, rho);
+        gcast_w<double>(d.rho[pout])[oidx] = rho;
+        gcast_w<FT>(d.vx)[oidx] = (FT)vx;      // FP32 with FP32 storage
+        gcast_w<FT>(d.vy)[oidx] = (FT)vy;
+    }
+    return !(rho == rho) || !(vx - vx == 0.0) || !(vy - vy == 0.0);
+}
+
 // ---------------------------------------------------------------- flow step
 // One tile: psi over the tile plus a one-node ring in LDS, then forces,
 // velocity and collision on the tile.  INNER: every node of the tile and its
@@ -174,7 +297,6 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
     constexpr int NHALO = 2 * LW + 2 * BY;
     const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
     const bool pery = (d.flags & F_PERY) != 0;
-    const bool frozen = (d.flags & F_FROZEN) != 0;
     const int pin = (int)((d.par0 + k) & 1), pout = pin ^ 1;
     const FT PB_GAS *fin = gcast<FT>(d.f[pin]);
     const double PB_GAS *rin = gcast<double>(d.rho[pin]);
@@ -235,12 +357,7 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
         }
         __syncthreads();
         decode_lds<RW>(s_rho, tx + 2, ty + 2, v, f);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            rho += f[i];
-            jx += kEX[i] * f[i];
-            jy += kEY[i] * f[i];
-        }
+        node_moments(f, rho, jx, jy);
         psi = eos_psi(d, rho, Tn, bad);
         s_psi[(ty + 1) * LW + tx + 1] = psi;
         if (has_h) {
@@ -255,12 +372,7 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
         if (live) {
             if (INNER) pull_inner<FT>(fin, rin, plane, pitch, idx, f);
             else pull_node<FT>(d, fin, rin, xw, yw, pery, f);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                rho += f[i];
-                jx += kEX[i] * f[i];
-                jy += kEY[i] * f[i];
-            }
+            node_moments(f, rho, jx, jy);
             psi = eos_psi(d, rho, Tt[toff + idx], bad);
         }
         s_psi[(ty + 1) * LW + tx + 1] = psi;
@@ -290,93 +402,22 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
     __syncthreads();
 
     if (own) {
-        // Eq. 11 over fluid neighbours, Eq. 14 over wall neighbours
-        double sfx = 0.0, sfy = 0.0, sax = 0.0, say = 0.0;
+        double pn[9], gw[9];
+        uint32_t wmask = 0;
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
             const int yn = yr + kEY[i];
             const bool wall = !INNER && !pery && (yn < 0 || yn >= d.nyf);
-            if (!wall) {
-                const double pn = s_psi[(ty + 1 + kEY[i]) * LW + tx + 1 + kEX[i]];
-                sfx += kWF[i] * kEX[i] * pn;
-                sfy += kWF[i] * kEY[i] * pn;
-            } else {
+            pn[i] = s_psi[(ty + 1 + kEY[i]) * LW + tx + 1 + kEX[i]];
+            gw[i] = 0.0;
+            if (wall) {
                 const int xn = wrap_once(xr + kEX[i], d.nx);
-                const double gam = (yn < 0) ? d.gbot[xn] : d.gtop[xn];
-                sax += kWF[i] * kEX[i] * gam;
-                say += kWF[i] * kEY[i] * gam;
+                gw[i] = (yn < 0) ? d.gbot[xn] : d.gtop[xn];
+                wmask |= 1u << i;
             }
         }
-        const double Fmx = -d.G * psi * sfx, Fmy = -d.G * psi * sfy;
-        const double Fax = -psi * sax, Fay = -psi * say;
-        const double Fx = Fmx + Fax;
-        const double Fy = Fmy + Fay - (rho - d.rho_bar) * d.g;       // Eq. 15
-        const double inv_rho = frcp(rho);
-        double vx = (jx + 0.5 * Fx) * inv_rho;                         // Eq. 10
-        double vy = (jy + 0.5 * Fy) * inv_rho;
-        if (frozen) { vx = 0.0; vy = 0.0; }
-        const uint32_t oidx = (uint32_t)yr * pitch + (uint32_t)xr;
-
-        if constexpr (MODE == PB_MODE_READ) {
-            double PB_GAS *rdf = gcast_w<double>(d.rd_f);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) (rdf + (uint32_t)i * plane)[oidx] = f[i];
-            gcast_w<double>(d.rd_rho)[oidx] = rho;
-            gcast_w<double>(d.rd_vx)[oidx] = vx;
-            gcast_w<double>(d.rd_vy)[oidx] = vy;
-        } else {
-            // moments m = M f (Eq. 6)
-            const double sa = f[1] + f[2] + f[3] + f[4];
-            const double sd = f[5] + f[6] + f[7] + f[8];
-            const double m1 = -4.0 * f[0] - sa + 2.0 * sd;
-            const double m2 = 4.0 * f[0] - 2.0 * sa + sd;
-            const double m4 = -2.0 * f[1] + 2.0 * f[3] + f[5] - f[6] - f[7] + f[8];
-            const double m6 = -2.0 * f[2] + 2.0 * f[4] + f[5] + f[6] - f[7] - f[8];
-            const double m7 = f[1] - f[2] + f[3] - f[4];
-            const double m8 = f[5] - f[6] + f[7] - f[8];
-            // equilibria (Eq. 6) with u = v of Eq. 10
-            const double u2 = vx * vx + vy * vy;
-            const double meq1 = rho * (-2.0 + 3.0 * u2), meq2 = rho * (1.0 - 3.0 * u2);
-            const double meq4 = -rho * vx, meq6 = -rho * vy;
-            const double meq7 = rho * (vx * vx - vy * vy), meq8 = rho * vx * vy;
-            // forcing of Eq. 9; the varpi term times (1 - s_e/2) equals
-            // 12 varpi s_e |F|^2 / psi^2 because tau_e = 1/s_e
-            const double Fwx = (d.flags & F_FMONLY) ? Fmx : Fmx + Fax;
-            const double Fwy = (d.flags & F_FMONLY) ? Fmy : Fmy + Fay;
-            const double uF = vx * Fx + vy * Fy;
-            const double cw = 12.0 * d.varpi * d.s_e * (Fwx * Fwx + Fwy * Fwy) * frcp(psi * psi);
-            const double cw2 = (d.flags & F_S2PLUS) ? cw : -cw;
-            const double se = d.s_e, sq = d.s_q;
-            const double snu = frcp(d.tau_V + (rho - d.rho_V) * d.ktau);   // Eq. 5
-            const double ms1 = m1 - se * (m1 - meq1) + (1.0 - 0.5 * se) * (6.0 * uF) + cw;
-            const double ms2 = m2 - se * (m2 - meq2) + (1.0 - 0.5 * se) * (-6.0 * uF) + cw2;
-            const double ms3 = jx + Fx;                       // s_j drops out (Eq. 7 + Eq. 10)
-            const double ms4 = m4 - sq * (m4 - meq4) + (1.0 - 0.5 * sq) * (-Fx);
-            const double ms5 = jy + Fy;
-            const double ms6 = m6 - sq * (m6 - meq6) + (1.0 - 0.5 * sq) * (-Fy);
-            const double ms7 = m7 - snu * (m7 - meq7) + (1.0 - 0.5 * snu) * (2.0 * (vx * Fx - vy * Fy));
-            const double ms8 = m8 - snu * (m8 - meq8) + (1.0 - 0.5 * snu) * (vx * Fy + vy * Fx);
-            // f* = M^{-1} m*, M^{-1} = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
-            const double a0 = rho * (1.0 / 9.0), a1 = ms1 * (1.0 / 36.0), a2 = ms2 * (1.0 / 36.0);
-            const double a3 = ms3 * (1.0 / 6.0), a4 = ms4 * (1.0 / 12.0), a5 = ms5 * (1.0 / 6.0);
-            const double a6 = ms6 * (1.0 / 12.0), a7 = ms7 * 0.25, a8 = ms8 * 0.25;
-            const double c0 = a0 - a1 - 2.0 * a2;       // axis-common part
-            const double cd = a0 + 2.0 * a1 + a2;       // diagonal-common part
-            FT PB_GAS *fout = gcast_w<FT>(d.f[pout]);
-            store_pop<FT>(fout, plane, oidx, 0, a0 - 4.0 * a1 + 4.0 * a2, rho);
-            store_pop<FT>(fout, plane, oidx, 1, c0 + a3 - 2.0 * a4 + a7, rho);
-            store_pop<FT>(fout, plane, oidx, 2, c0 + a5 - 2.0 * a6 - a7, rho);
-            store_pop<FT>(fout, plane, oidx, 3, c0 - a3 + 2.0 * a4 + a7, rho);
-            store_pop<FT>(fout, plane, oidx, 4, c0 - a5 + 2.0 * a6 - a7, rho);
-            store_pop<FT>(fout, plane, oidx, 5, cd + a3 + a4 + a5 + a6 + a8, rho);
-            store_pop<FT>(fout, plane, oidx, 6, cd - a3 - a4 + a5 + a6 - a8, rho);
-            store_pop<FT>(fout, plane, oidx, 7, cd - a3 - a4 - a5 - a6 + a8, rho);
-            store_pop<FT>(fout, plane, oidx, 8, cd + a3 + a4 - a5 - a6 - a8, rho);
-            gcast_w<double>(d.rho[pout])[oidx] = rho;
-            gcast_w<FT>(d.vx)[oidx] = (FT)vx;      // FP32 with FP32 storage
-            gcast_w<FT>(d.vy)[oidx] = (FT)vy;
-        }
-        if (bad || !(rho == rho) || !(vx - vx == 0.0) || !(vy - vy == 0.0)) *s_bad = 1;
+        if (node_update<FT, MODE>(d, f, rho, jx, jy, psi, pn, gw, wmask, (uint32_t)yr * pitch + (uint32_t)xr, pout) || bad)
+            *s_bad = 1;
     }
 }
 
@@ -402,6 +443,183 @@ __global__ __launch_bounds__(BX *BY) void k_flow(const PbDesc *const *__restrict
     }
 }
 
+// ------------------------------------------------------- flow step (sweep)
+// Column-sweep form of the same step.  One wavefront owns 64 consecutive
+// columns (the middle 60 are written; two on each side are halo) and walks up
+// a strip of H fluid rows.  At row r it pulls the populations (Eq. 8) and
+// forms rho, j and psi there, then updates row r-1, whose psi neighbours
+// (rows r-2..r) are in registers and whose x-neighbours come from the
+// adjacent lanes; the loads of row r+1 are in flight meanwhile.  No LDS, no
+// barriers, and every population row is read once per strip.
+
+// pulled-state inputs of one row: the nine stored values, T(t-1) of the row
+// and, for the FP32 decode, rho(t-1) of the row above
+template <typename FT>
+struct SweepRow {
+    FT v[9];
+    double T, rn;
+};
+
+// IN: the strip and its halo rows (y0 - 2 .. y0 + H + 1) lie inside a walled
+// fluid, so no row wraps, bounces back or sees a wall.
+template <typename FT, int H, int UNR, int MODE, bool IN>
+__device__ __forceinline__ bool flow_strip(cdesc &d, const PbTile &te, int k, int lane) {
+    constexpr bool F32 = std::is_same<FT, float>::value;
+    const bool pery = !IN && (d.flags & F_PERY) != 0;
+    const int nx = d.nx, nyf = d.nyf;
+    const int pin = (int)((d.par0 + k) & 1), pout = pin ^ 1;
+    const FT PB_GAS *fin = gcast<FT>(d.f[pin]);
+    const double PB_GAS *rin = gcast<double>(d.rho[pin]);
+    const double PB_GAS *Tt = gcast<double>(d.T[pin]);
+    const uint32_t pitch = (uint32_t)d.pitch, plane = (uint32_t)nyf * pitch;
+    const uint32_t toff = (uint32_t)d.nys * pitch;           // fluid row 0 in the T array
+    // lanes map to consecutive columns modulo nx (any nx >= 1)
+    int xg = (te.x0 - 2 + lane) % nx;
+    if (xg < 0) xg += nx;
+    const int xm = xg == 0 ? nx - 1 : xg - 1, xp = xg == nx - 1 ? 0 : xg + 1;
+    const bool out_lane = lane >= 2 && lane < 62 && te.x0 + lane - 2 < nx;
+
+    // row r as stored (wrapped when periodic); false outside a walled fluid
+    auto row_of = [&](int r, int &rr) -> bool {
+        rr = r;
+        if (IN) return true;
+        if (pery) {
+            rr %= nyf;
+            if (rr < 0) rr += nyf;
+            return true;
+        }
+        return r >= 0 && r < nyf;
+    };
+    auto load_row = [&](int r, SweepRow<FT> &p) {
+        int rr;
+        if constexpr (F32) p.rn = row_of(r + 1, rr) ? rin[(uint32_t)rr * pitch + (uint32_t)xg] : 0.0;
+        if (!row_of(r, rr)) return;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            int ys = rr - kEY[i], xs = kEX[i] > 0 ? xm : (kEX[i] < 0 ? xp : xg), ii = i;
+            if (IN) {
+            } else if (pery) {
+                ys = wrap_once(ys, nyf);
+            } else if (ys < 0 || ys >= nyf) {        // halfway bounce-back
+                ii = kOPP[i];
+                xs = xg;
+                ys = rr;
+            }
+            p.v[i] = (fin + (uint32_t)ii * plane)[(uint32_t)ys * pitch + (uint32_t)xs];
+        }
+        p.T = Tt[toff + (uint32_t)rr * pitch + (uint32_t)xg];
+    };
+
+    // rho(t-1) of rows r-1 (m*), r (c*) at columns x-1 (L), x, x+1 (R)
+    double mL = 0.0, mC = 0.0, mR = 0.0, cL = 0.0, cC = 0.0, cR = 0.0;
+    // psi of rows r-1 (p1*) and r-2 (p2*)
+    double p1L = 0.0, p1C = 0.0, p1R = 0.0, p2L = 0.0, p2C = 0.0, p2R = 0.0;
+    // pulled state of row r-1
+    double fp[9], rho_p = 0.0, jx_p = 0.0, jy_p = 0.0;
+    bool bad_p = false, bad = false;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fp[i] = 0.0;
+
+    const int r0 = te.y0 - 1;
+    if constexpr (F32) {
+        int rr;
+        if (row_of(r0 - 1, rr)) mC = rin[(uint32_t)rr * pitch + (uint32_t)xg];
+        if (row_of(r0, rr)) cC = rin[(uint32_t)rr * pitch + (uint32_t)xg];
+        mL = from_left(mC); mR = from_right(mC);
+        cL = from_left(cC); cR = from_right(cC);
+    }
+    SweepRow<FT> nxt{};
+    load_row(r0, nxt);
+#pragma unroll UNR
+    for (int j = 0; j < H + 2; ++j) {
+        const int r = r0 + j;
+        const SweepRow<FT> cur = nxt;
+        if (j + 1 < H + 2) load_row(r + 1, nxt);
+
+        // rho(t-1) of row r+1
+        double nC = 0.0, nL = 0.0, nR = 0.0;
+        if constexpr (F32) {
+            nC = cur.rn;
+            nL = from_left(nC);
+            nR = from_right(nC);
+        }
+        // pull of row r: decode, moments, psi
+        int rr;
+        const bool live = row_of(r, rr);
+        double f[9], rho = 0.0, jx = 0.0, jy = 0.0, psi = 0.0;
+        bool bad_r = false;
+        if (live) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                if constexpr (F32) {
+                    const int ys = rr - kEY[i];
+                    const bool bb = !IN && !pery && (ys < 0 || ys >= nyf);
+                    double rs;
+                    if (bb) rs = cC;
+                    else if (kEY[i] > 0) rs = kEX[i] > 0 ? mL : (kEX[i] < 0 ? mR : mC);
+                    else if (kEY[i] < 0) rs = kEX[i] > 0 ? nL : (kEX[i] < 0 ? nR : nC);
+                    else rs = kEX[i] > 0 ? cL : (kEX[i] < 0 ? cR : cC);
+                    f[i] = kW[i] * rs + (double)cur.v[i];
+                } else {
+                    f[i] = cur.v[i];
+                }
+            }
+            node_moments(f, rho, jx, jy);
+            psi = eos_psi(d, rho, cur.T, bad_r);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) f[i] = 0.0;
+        }
+        const double psL = from_left(psi), psR = from_right(psi);
+
+        // update of row q = r-1 (psi rows r-2, r-1, r)
+        const int q = r - 1;
+        if (j >= 2 && (IN || q < nyf) && out_lane) {
+            double pn[9], gw[9];
+            uint32_t wmask = 0;
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                if (kEY[i] > 0) pn[i] = kEX[i] > 0 ? psR : (kEX[i] < 0 ? psL : psi);
+                else if (kEY[i] < 0) pn[i] = kEX[i] > 0 ? p2R : (kEX[i] < 0 ? p2L : p2C);
+                else pn[i] = kEX[i] > 0 ? p1R : (kEX[i] < 0 ? p1L : p1C);
+                gw[i] = 0.0;
+                const int yn = q + kEY[i];
+                if (!IN && !pery && (yn < 0 || yn >= nyf)) {
+                    const int xn = kEX[i] > 0 ? xp : (kEX[i] < 0 ? xm : xg);
+                    gw[i] = (yn < 0) ? d.gbot[xn] : d.gtop[xn];
+                    wmask |= 1u << i;
+                }
+            }
+            const bool nf = node_update<FT, MODE>(d, fp, rho_p, jx_p, jy_p, p1C, pn, gw, wmask,
+                                                  (uint32_t)q * pitch + (uint32_t)xg, pout);
+            bad = bad || nf || bad_p;
+        }
+
+        // shift the windows by one row
+        mL = cL; mC = cC; mR = cR;
+        cL = nL; cC = nC; cR = nR;
+        p2L = p1L; p2C = p1C; p2R = p1R;
+        p1L = psL; p1C = psi; p1R = psR;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) fp[i] = f[i];
+        rho_p = rho; jx_p = jx; jy_p = jy; bad_p = bad_r;
+    }
+    return bad;
+}
+
+template <typename FT, int H, int UNR, int MODE>
+__global__ __launch_bounds__(64) void k_flow_sweep(const PbDesc *const *__restrict__ dps,
+                                                    const PbTile *__restrict__ tiles, int ntiles, int k) {
+    for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+        const PbTile te = tiles[tl];
+        cdesc &d = *(const PbDesc PB_CAS *)dps[te.dom];
+        const bool in = !(d.flags & F_PERY) && te.y0 >= 2 && te.y0 + H + 1 < d.nyf;
+        const bool nf = in ? flow_strip<FT, H, UNR, MODE, true>(d, te, k, threadIdx.x)
+                           : flow_strip<FT, H, UNR, MODE, false>(d, te, k, threadIdx.x);
+        if (nf) flag_error(d);
+    }
+}
+
 // Thermal node kinds.
 enum : int { KIND_NONE = 0, KIND_FIXED = 1, KIND_SOLID = 2, KIND_FLUID = 3 };
 
@@ -421,18 +639,6 @@ struct Coef9 {
     double k0, k1, k2, k3, k4, k5, k6, k7, k8, beta;
 };
 
-// Lane exchange with DPP wave shifts (a VALU move, no LDS round trip): wave_shr:1
-// gives lane i the value of lane i-1 (column x-1), wave_shl:1 that of lane i+1.
-// The end lanes receive 0; they are halo columns whose results are discarded.
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v) {
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
-}
-__device__ __forceinline__ double from_left(double v) { return dpp_move<0x138>(v); }   // value at x-1
-__device__ __forceinline__ double from_right(double v) { return dpp_move<0x130>(v); }  // value at x+1
 
 // harmonic-mean link conductance; a negative value marks the T_top row, whose
 // links take the conductance of the other node
@@ -766,7 +972,10 @@ __global__ void k_advance(PbDesc *const *__restrict__ dps, int ndom, int nsteps)
 
 // ------------------------------------------------------------ launch helpers
 // Flow tile variants: (BX, BY) with BX * BY threads per block.
-static const int kFlowShapes[][2] = {{64, 4}, {64, 8}, {32, 8}, {128, 4}, {32, 16}, {64, 16}};
+// tiles of BX x BY nodes (one block of BX * BY threads each), then column
+// sweeps of 60 written columns x H rows (one wavefront each)
+static const int kFlowShapes[][2] = {{64, 4}, {64, 8}, {32, 8}, {128, 4}, {32, 16}, {64, 16},
+                                     {60, 8}, {60, 16}, {60, 32}};
 // column sweeps of 56 written columns x H rows
 // the whole strip is unrolled so the operator ring lives in registers
 static const int kThermalShapes[][2] = {{56, 28}, {56, 20}, {56, 24}, {56, 16}};
@@ -797,6 +1006,14 @@ static hipError_t launch_flow_t(int variant, const PbDesc *const *dps, const PbT
         PB_FLOW_CASE(4, 32, 16)
         PB_FLOW_CASE(5, 64, 16)
 #undef PB_FLOW_CASE
+#define PB_SWEEP_CASE(V, H, UNR)                                                                       \
+    case V:                                                                                           \
+        hipLaunchKernelGGL((k_flow_sweep<FT, H, UNR, MODE>), dim3(grid), dim3(64), 0, s, dps, t, nt, k); \
+        break;
+        PB_SWEEP_CASE(6, 8, 10)
+        PB_SWEEP_CASE(7, 16, 18)
+        PB_SWEEP_CASE(8, 32, 2)
+#undef PB_SWEEP_CASE
         default:
             return hipErrorInvalidValue;
     }

@@ -25,14 +25,19 @@ def _report(name, errs):
     print(name, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
 
 
+# default tiles (64x4 blocks) and a column sweep of 60 columns x 16 rows
+FLOW_FAMILIES = [(0, 0), (60, 16)]
+
+
+@pytest.mark.parametrize("tile", FLOW_FAMILIES)
 @pytest.mark.parametrize("precision", [0, 1])
-def test_pool_boiling_100x100_200_steps(precision):
+def test_pool_boiling_100x100_200_steps(precision, tile):
     """Plain pool boiling, 100x100 fluid over a 100x10 heater, liquid below
     y = 40, heater bottom at Tsat + 0.1 Tc with 4 seeded +2% spots."""
     P, d, bc, rho, T = pool_case(100, 100, 10, superheat=0.1, n_spots=4, seed=0, y0=40)
-    g, o = run_pair(P, bc, rho, T, steps=200, precision=precision, window=(50, 201, 10))
+    g, o = run_pair(P, bc, rho, T, steps=200, precision=precision, tile=tile, window=(50, 201, 10))
     errs = compare(g, o)
-    _report(f"C0 prec={precision}", errs)
+    _report(f"C0 prec={precision} tile={tile}", errs)
     assert all(v <= TOL[precision] for v in errs.values()), errs
     for k in ("q_bottom_mean", "q_top_mean", "T_w_mean", "q_bottom_inst"):
         assert g["flux"][k] == pytest.approx(o["flux"][k], rel=TOL[precision] * 10, abs=1e-15), k
@@ -45,7 +50,7 @@ def test_ragged_domain_and_tile_shapes_are_bit_identical():
     every thermal variant."""
     P, d, bc, rho, T = pool_case(77, 45, 5, superheat=0.2, n_spots=3, seed=7, y0=17)
     ref = None
-    shapes = [(64, 4), (64, 8), (32, 8), (128, 4), (32, 16), (64, 16), (64, 4)]
+    shapes = [(64, 4), (64, 8), (32, 8), (128, 4), (32, 16), (64, 16), (60, 8), (60, 16), (60, 32), (64, 4)]
     for i, tile in enumerate(shapes):
         g = gpu_domain(P, bc, rho, T, 0, tile=tile, thermal_tile=i % 4)
         g.step(120)
@@ -64,8 +69,9 @@ def test_ragged_domain_and_tile_shapes_are_bit_identical():
                 np.testing.assert_array_equal(r[k], ref[k], err_msg=f"{k} differs for tile {tile}")
 
 
+@pytest.mark.parametrize("tile", [(0, 0), (60, 8)])
 @pytest.mark.parametrize("isothermal", [1, 0])
-def test_periodic_drop(isothermal):
+def test_periodic_drop(isothermal, tile):
     """Fully periodic box with a drop (no walls, no heater): exercises the
     periodic wrap in y of streaming, forces and the thermal stencil."""
     nx, ny = 48, 40
@@ -73,9 +79,9 @@ def test_periodic_drop(isothermal):
     rho = W.drop_rho(nx, ny, 9.0, d["rho_L"], d["rho_V"], width=3.0, cx=20.3, cy=17.6)
     T = W.perturbed(np.full((ny, nx), d["Tsat"]), 0.02, 11)
     bc = dict(T_top=d["Tsat"])
-    g, o = run_pair(P, bc, rho, T, steps=200, precision=0)
+    g, o = run_pair(P, bc, rho, T, steps=200, precision=0, tile=tile)
     errs = compare(g, o)
-    _report(f"drop iso={isothermal}", errs)
+    _report(f"drop iso={isothermal} tile={tile}", errs)
     assert all(v <= 1e-11 for v in errs.values()), errs
 
 
@@ -94,14 +100,15 @@ def test_frozen_flow_conduction():
     assert g["flux"]["q_bottom_mean"] == pytest.approx(o["flux"]["q_bottom_mean"], rel=1e-11)
 
 
+@pytest.mark.parametrize("tile", [(0, 0), (60, 8)])
 @pytest.mark.parametrize("shape", [(1, 1, 3), (2, 3, 3), (3, 70, 4), (130, 2, 3)])
-def test_degenerate_shapes(shape):
+def test_degenerate_shapes(shape, tile):
     """Single column, two-row fluid, tall-thin and wide-flat domains."""
     nx, nyf, nys = shape
     P, d, bc, rho, T = pool_case(nx, nyf, nys, superheat=0.15, n_spots=0, y0=max(1, nyf // 2))
-    g, o = run_pair(P, bc, rho, T, steps=60, precision=0)
+    g, o = run_pair(P, bc, rho, T, steps=60, precision=0, tile=tile)
     errs = compare(g, o)
-    _report(f"shape {shape}", errs)
+    _report(f"shape {shape} tile={tile}", errs)
     assert all(v <= 1e-11 for v in errs.values()), errs
 
 
