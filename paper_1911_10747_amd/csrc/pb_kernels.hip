@@ -152,14 +152,65 @@ __device__ __forceinline__ void decode_lds(const double *s_rho, int lx, int ly, 
     for (int i = 0; i < 9; ++i) f[i] = kW[i] * s_rho[(ly - kEY[i]) * RW + lx - kEX[i]] + (double)v[i];
 }
 
+// FP32 storage keeps f* - w_i rho(t) (the deviation), FP64 storage f* itself
 template <typename FT>
-__device__ __forceinline__ void store_pop(FT PB_GAS *fout, uint32_t plane, uint32_t idx, int i, double fs,
-                                          double rho) {
+__device__ __forceinline__ FT encode_pop(int i, double fs, double rho) {
     if constexpr (std::is_same<FT, float>::value)
-        (fout + (uint32_t)i * plane)[idx] = (float)(fs - kW[i] * rho);
+        return (float)(fs - kW[i] * rho);
     else
-        (fout + (uint32_t)i * plane)[idx] = fs;
+        return fs;
 }
+
+// Where a node's outputs go: through global pointers at element offset oidx...
+template <typename FT>
+struct GlobalStore {
+    FT PB_GAS *f;
+    double PB_GAS *rho;
+    FT PB_GAS *vx;
+    FT PB_GAS *vy;
+    uint32_t plane, oidx;
+    __device__ __forceinline__ void pop(int i, FT v) const { (f + (uint32_t)i * plane)[oidx] = v; }
+    __device__ __forceinline__ void fields(double r, FT ux, FT uy) const {
+        rho[oidx] = r;
+        vx[oidx] = ux;
+        vy[oidx] = uy;
+    }
+};
+
+// ...or through buffer resources: a per-lane column byte offset (vf for FT
+// arrays, vd for FP64 ones) plus a uniform row byte offset (sf, sd).
+typedef unsigned int pb_u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <typename T>
+__device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(pb_u32x2, v), r, voff, soff, 0);
+}
+template <typename FT>
+struct BufferStore {
+    __amdgpu_buffer_rsrc_t rs;          // one resource over the domain's arrays
+    uint32_t of, orho, ovx, ovy;        // array byte offsets from its base
+    uint32_t vf, vd, sf, sd, plane_bytes;
+    __device__ __forceinline__ void pop(int i, FT v) const {
+        buf_store<FT>(v, rs, vf, of + sf + (uint32_t)i * plane_bytes);
+    }
+    __device__ __forceinline__ void fields(double r, FT ux, FT uy) const {
+        buf_store<double>(r, rs, vd, orho + sd);
+        buf_store<FT>(ux, rs, vf, ovx + sf);
+        buf_store<FT>(uy, rs, vf, ovy + sf);
+    }
+};
 
 // Lane exchange with DPP wave shifts (a VALU move, no LDS round trip): wave_shr:1
 // gives lane i the value of lane i-1 (column x-1), wave_shl:1 that of lane i+1.
@@ -175,30 +226,46 @@ __device__ __forceinline__ double from_left(double v) { return dpp_move<0x138>(v
 __device__ __forceinline__ double from_right(double v) { return dpp_move<0x130>(v); }  // value at x+1
 
 // ------------------------------------------------------------ node update
-// rho and momentum of the pulled populations (Eq. 10 without the force)
-__device__ __forceinline__ void node_moments(const double f[9], double &rho, double &jx, double &jy) {
-    rho = 0.0;
-    jx = 0.0;
-    jy = 0.0;
+// Moments of the pulled populations: rho and j (Eq. 10 without the force)
+// and the non-conserved rows of m = M f (Eq. 6) the collision relaxes.
+struct Mom {
+    double rho, jx, jy, m1, m2, m4, m6, m7, m8;
+};
+__device__ __forceinline__ Mom node_moments(const double f[9]) {
+    Mom m;
+    m.rho = 0.0;
+    m.jx = 0.0;
+    m.jy = 0.0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        rho += f[i];
-        jx += kEX[i] * f[i];
-        jy += kEY[i] * f[i];
+        m.rho += f[i];
+        m.jx += kEX[i] * f[i];
+        m.jy += kEY[i] * f[i];
     }
+    const double sa = f[1] + f[2] + f[3] + f[4];
+    const double sd = f[5] + f[6] + f[7] + f[8];
+    m.m1 = -4.0 * f[0] - sa + 2.0 * sd;
+    m.m2 = 4.0 * f[0] - 2.0 * sa + sd;
+    m.m4 = -2.0 * f[1] + 2.0 * f[3] + f[5] - f[6] - f[7] + f[8];
+    m.m6 = -2.0 * f[2] + 2.0 * f[4] + f[5] + f[6] - f[7] - f[8];
+    m.m7 = f[1] - f[2] + f[3] - f[4];
+    m.m8 = f[5] - f[6] + f[7] - f[8];
+    return m;
 }
 
-// Forces, velocity and collision of one fluid node from its pulled
-// populations f, rho, j, its psi and, for i = 1..8, psi of the neighbour
+// Forces, velocity and collision of one fluid node from the moments mo of its
+// pulled populations f (f itself is used in read mode only), its psi and,
+// for i = 1..8, psi of the neighbour
 // x + e_i (pn[i]) or, where bit i of wmask marks that neighbour as a wall,
 // the wall's adhesion gamma (gw[i]).  Writes f*, rho(t), v(t) at oidx (or, in
 // read mode, the pulled state).  Returns true if the node is not finite.
 // Every flow kernel updates its nodes through this one function, so a node
 // gives the same bits whatever the launch shape.
-template <typename FT, int MODE>
-__device__ __forceinline__ bool node_update(cdesc &d, const double f[9], double rho, double jx, double jy,
-                                            double psi, const double pn[9], const double gw[9], uint32_t wmask,
-                                            uint32_t oidx, int pout) {
+template <typename FT, int MODE, typename ST>
+__device__ __forceinline__ bool node_update(cdesc &d, const double f[9], const Mom &mo, double psi,
+                                            const double pn[9], const double gw[9], uint32_t wmask, uint32_t oidx,
+                                            const ST &st) {
+    const double rho = mo.rho, jx = mo.jx, jy = mo.jy;
     const bool frozen = (d.flags & F_FROZEN) != 0;
     const uint32_t plane = (uint32_t)d.nyf * (uint32_t)d.pitch;
     // Eq. 11 over fluid neighbours, Eq. 14 over wall neighbours
@@ -230,15 +297,7 @@ __device__ __forceinline__ bool node_update(cdesc &d, const double f[9], double 
         gcast_w<double>(d.rd_vx)[oidx] = vx;
         gcast_w<double>(d.rd_vy)[oidx] = vy;
     } else {
-        // moments m = M f (Eq. 6)
-        const double sa = f[1] + f[2] + f[3] + f[4];
-        const double sd = f[5] + f[6] + f[7] + f[8];
-        const double m1 = -4.0 * f[0] - sa + 2.0 * sd;
-        const double m2 = 4.0 * f[0] - 2.0 * sa + sd;
-        const double m4 = -2.0 * f[1] + 2.0 * f[3] + f[5] - f[6] - f[7] + f[8];
-        const double m6 = -2.0 * f[2] + 2.0 * f[4] + f[5] + f[6] - f[7] - f[8];
-        const double m7 = f[1] - f[2] + f[3] - f[4];
-        const double m8 = f[5] - f[6] + f[7] - f[8];
+        const double m1 = mo.m1, m2 = mo.m2, m4 = mo.m4, m6 = mo.m6, m7 = mo.m7, m8 = mo.m8;
         // equilibria (Eq. 6) with u = v of Eq. 10
         const double u2 = vx * vx + vy * vy;
         const double meq1 = rho * (-2.0 + 3.0 * u2), meq2 = rho * (1.0 - 3.0 * u2);
@@ -267,19 +326,16 @@ __device__ __forceinline__ bool node_update(cdesc &d, const double f[9], double 
         const double a6 = ms6 * (1.0 / 12.0), a7 = ms7 * 0.25, a8 = ms8 * 0.25;
         const double c0 = a0 - a1 - 2.0 * a2;       // axis-common part
         const double cd = a0 + 2.0 * a1 + a2;       // diagonal-common part
-        FT PB_GAS *fout = gcast_w<FT>(d.f[pout]);
-        store_pop<FT>(fout, plane, oidx, 0, a0 - 4.0 * a1 + 4.0 * a2, rho);
-        store_pop<FT>(fout, plane, oidx, 1, c0 + a3 - 2.0 * a4 + a7, rho);
-        store_pop<FT>(fout, plane, oidx, 2, c0 + a5 - 2.0 * a6 - a7, rho);
-        store_pop<FT>(fout, plane, oidx, 3, c0 - a3 + 2.0 * a4 + a7, rho);
-        store_pop<FT>(fout, plane, oidx, 4, c0 - a5 + 2.0 * a6 - a7, rho);
-        store_pop<FT>(fout, plane, oidx, 5, cd + a3 + a4 + a5 + a6 + a8, rho);
-        store_pop<FT>(fout, plane, oidx, 6, cd - a3 - a4 + a5 + a6 - a8, rho);
-        store_pop<FT>(fout, plane, oidx, 7, cd - a3 - a4 - a5 - a6 + a8, rho);
-        store_pop<FT>(fout, plane, oidx, 8, cd + a3 + a4 - a5 - a6 - a8, rho);
-        gcast_w<double>(d.rho[pout])[oidx] = rho;
-        gcast_w<FT>(d.vx)[oidx] = (FT)vx;      // FP32 with FP32 storage
-        gcast_w<FT>(d.vy)[oidx] = (FT)vy;
+        st.pop(0, encode_pop<FT>(0, a0 - 4.0 * a1 + 4.0 * a2, rho));
+        st.pop(1, encode_pop<FT>(1, c0 + a3 - 2.0 * a4 + a7, rho));
+        st.pop(2, encode_pop<FT>(2, c0 + a5 - 2.0 * a6 - a7, rho));
+        st.pop(3, encode_pop<FT>(3, c0 - a3 + 2.0 * a4 + a7, rho));
+        st.pop(4, encode_pop<FT>(4, c0 - a5 + 2.0 * a6 - a7, rho));
+        st.pop(5, encode_pop<FT>(5, cd + a3 + a4 + a5 + a6 + a8, rho));
+        st.pop(6, encode_pop<FT>(6, cd - a3 - a4 + a5 + a6 - a8, rho));
+        st.pop(7, encode_pop<FT>(7, cd - a3 - a4 - a5 - a6 + a8, rho));
+        st.pop(8, encode_pop<FT>(8, cd + a3 + a4 - a5 - a6 - a8, rho));
+        st.fields(rho, (FT)vx, (FT)vy);      // v in FP32 with FP32 storage
     }
     return !(rho == rho) || !(vx - vx == 0.0) || !(vy - vy == 0.0);
 }
@@ -312,7 +368,8 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
     const int xw = INNER ? xr : xr - (xr >= d.nx ? d.nx : 0);
     const int yw = (INNER || !pery) ? yr : yr - (yr >= d.nyf ? d.nyf : 0);
     const bool live = INNER || (xw < d.nx && yw < d.nyf);
-    double f[9], rho = 0.0, jx = 0.0, jy = 0.0, psi = 0.0;
+    double f[9], psi = 0.0;
+    Mom mo{};
     const uint32_t idx = (uint32_t)yw * pitch + (uint32_t)xw;
 
     // ring node of psi around the tile handled by this thread, if any
@@ -357,8 +414,8 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
         }
         __syncthreads();
         decode_lds<RW>(s_rho, tx + 2, ty + 2, v, f);
-        node_moments(f, rho, jx, jy);
-        psi = eos_psi(d, rho, Tn, bad);
+        mo = node_moments(f);
+        psi = eos_psi(d, mo.rho, Tn, bad);
         s_psi[(ty + 1) * LW + tx + 1] = psi;
         if (has_h) {
             double fh[9], rh = 0.0;
@@ -372,8 +429,8 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
         if (live) {
             if (INNER) pull_inner<FT>(fin, rin, plane, pitch, idx, f);
             else pull_node<FT>(d, fin, rin, xw, yw, pery, f);
-            node_moments(f, rho, jx, jy);
-            psi = eos_psi(d, rho, Tt[toff + idx], bad);
+            mo = node_moments(f);
+            psi = eos_psi(d, mo.rho, Tt[toff + idx], bad);
         }
         s_psi[(ty + 1) * LW + tx + 1] = psi;
         if (has_h) {
@@ -416,7 +473,10 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
                 wmask |= 1u << i;
             }
         }
-        if (node_update<FT, MODE>(d, f, rho, jx, jy, psi, pn, gw, wmask, (uint32_t)yr * pitch + (uint32_t)xr, pout) || bad)
+        const uint32_t oidx = (uint32_t)yr * pitch + (uint32_t)xr;
+        const GlobalStore<FT> st{gcast_w<FT>(d.f[pout]), gcast_w<double>(d.rho[pout]), gcast_w<FT>(d.vx),
+                                 gcast_w<FT>(d.vy), plane, oidx};
+        if (node_update<FT, MODE>(d, f, mo, psi, pn, gw, wmask, oidx, st) || bad)
             *s_bad = 1;
     }
 }
@@ -454,6 +514,29 @@ __global__ __launch_bounds__(BX *BY) void k_flow(const PbDesc *const *__restrict
 
 // pulled-state inputs of one row: the nine stored values, T(t-1) of the row
 // and, for the FP32 decode, rho(t-1) of the row above
+// Lowest address and byte span of the arrays a flow step touches.
+__device__ __forceinline__ const char *arena_lo(cdesc &d) {
+    const char *p[8] = {(const char *)d.f[0], (const char *)d.f[1], (const char *)d.rho[0], (const char *)d.rho[1],
+                        (const char *)d.vx, (const char *)d.vy, (const char *)d.T[0], (const char *)d.T[1]};
+    const char *lo = p[0];
+#pragma unroll
+    for (int i = 1; i < 8; ++i) lo = p[i] < lo ? p[i] : lo;
+    return lo;
+}
+template <typename FT>
+__device__ __forceinline__ uint64_t arena_span(cdesc &d) {
+    const uint64_t plane = (uint64_t)d.nyf * (uint64_t)d.pitch, tp = (uint64_t)d.nr * (uint64_t)d.pitch;
+    const char *lo = arena_lo(d);
+    const char *e[8] = {(const char *)d.f[0] + 9 * plane * sizeof(FT), (const char *)d.f[1] + 9 * plane * sizeof(FT),
+                        (const char *)d.rho[0] + plane * 8, (const char *)d.rho[1] + plane * 8,
+                        (const char *)d.vx + plane * sizeof(FT), (const char *)d.vy + plane * sizeof(FT),
+                        (const char *)d.T[0] + tp * 8, (const char *)d.T[1] + tp * 8};
+    const char *hi = e[0];
+#pragma unroll
+    for (int i = 1; i < 8; ++i) hi = e[i] > hi ? e[i] : hi;
+    return (uint64_t)(hi - lo);
+}
+
 template <typename FT>
 struct SweepRow {
     FT v[9];
@@ -490,8 +573,27 @@ __device__ __forceinline__ bool flow_strip(cdesc &d, const PbTile &te, int k, in
         }
         return r >= 0 && r < nyf;
     };
+    // Interior strips address through one buffer resource over the domain's
+    // arrays: uniform array and row byte offsets in scalar registers, fixed
+    // per-lane column offsets (the caller has checked that the arrays span
+    // less than 2^32 bytes from the lowest of them).
+    constexpr uint32_t ES = sizeof(FT);
+    const char *lo = arena_lo(d);
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(lo, 0xFFFFFFFFu);
+    auto off = [&](const void *p) -> uint32_t { return (uint32_t)((const char *)p - lo); };
+    const uint32_t ofi = off(d.f[pin]), ori = off(d.rho[pin]), oTi = off(d.T[pin]);
+    const uint32_t cg = (uint32_t)xg * ES, cm = (uint32_t)xm * ES, cp = (uint32_t)xp * ES, cd = (uint32_t)xg * 8u;
     auto load_row = [&](int r, SweepRow<FT> &p) {
         int rr;
+        if constexpr (IN) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                p.v[i] = buf_load<FT>(rs, kEX[i] > 0 ? cm : (kEX[i] < 0 ? cp : cg),
+                                      ofi + ((uint32_t)i * plane + (uint32_t)(r - kEY[i]) * pitch) * ES);
+            p.T = buf_load<double>(rs, cd, oTi + (toff + (uint32_t)r * pitch) * 8u);
+            if constexpr (F32) p.rn = buf_load<double>(rs, cd, ori + (uint32_t)(r + 1) * pitch * 8u);
+            return;
+        }
         if constexpr (F32) p.rn = row_of(r + 1, rr) ? rin[(uint32_t)rr * pitch + (uint32_t)xg] : 0.0;
         if (!row_of(r, rr)) return;
 #pragma unroll
@@ -514,8 +616,9 @@ __device__ __forceinline__ bool flow_strip(cdesc &d, const PbTile &te, int k, in
     double mL = 0.0, mC = 0.0, mR = 0.0, cL = 0.0, cC = 0.0, cR = 0.0;
     // psi of rows r-1 (p1*) and r-2 (p2*)
     double p1L = 0.0, p1C = 0.0, p1R = 0.0, p2L = 0.0, p2C = 0.0, p2R = 0.0;
-    // pulled state of row r-1
-    double fp[9], rho_p = 0.0, jx_p = 0.0, jy_p = 0.0;
+    // pulled state of row r-1 (the populations themselves only in read mode)
+    double fp[9];
+    Mom mo_p{};
     bool bad_p = false, bad = false;
 #pragma unroll
     for (int i = 0; i < 9; ++i) fp[i] = 0.0;
@@ -546,7 +649,8 @@ __device__ __forceinline__ bool flow_strip(cdesc &d, const PbTile &te, int k, in
         // pull of row r: decode, moments, psi
         int rr;
         const bool live = row_of(r, rr);
-        double f[9], rho = 0.0, jx = 0.0, jy = 0.0, psi = 0.0;
+        double f[9], psi = 0.0;
+        Mom mo{};
         bool bad_r = false;
         if (live) {
 #pragma unroll
@@ -564,8 +668,8 @@ __device__ __forceinline__ bool flow_strip(cdesc &d, const PbTile &te, int k, in
                     f[i] = cur.v[i];
                 }
             }
-            node_moments(f, rho, jx, jy);
-            psi = eos_psi(d, rho, cur.T, bad_r);
+            mo = node_moments(f);
+            psi = eos_psi(d, mo.rho, cur.T, bad_r);
         } else {
 #pragma unroll
             for (int i = 0; i < 9; ++i) f[i] = 0.0;
@@ -590,8 +694,17 @@ __device__ __forceinline__ bool flow_strip(cdesc &d, const PbTile &te, int k, in
                     wmask |= 1u << i;
                 }
             }
-            const bool nf = node_update<FT, MODE>(d, fp, rho_p, jx_p, jy_p, p1C, pn, gw, wmask,
-                                                  (uint32_t)q * pitch + (uint32_t)xg, pout);
+            const uint32_t oidx = (uint32_t)q * pitch + (uint32_t)xg;
+            bool nf;
+            if constexpr (IN && MODE == PB_MODE_STEP) {
+                const BufferStore<FT> st{rs, off(d.f[pout]), off(d.rho[pout]), off(d.vx), off(d.vy),
+                                         cg, cd, (uint32_t)q * pitch * ES, (uint32_t)q * pitch * 8u, plane * ES};
+                nf = node_update<FT, MODE>(d, fp, mo_p, p1C, pn, gw, wmask, oidx, st);
+            } else {
+                const GlobalStore<FT> st{gcast_w<FT>(d.f[pout]), gcast_w<double>(d.rho[pout]), gcast_w<FT>(d.vx),
+                                         gcast_w<FT>(d.vy), plane, oidx};
+                nf = node_update<FT, MODE>(d, fp, mo_p, p1C, pn, gw, wmask, oidx, st);
+            }
             bad = bad || nf || bad_p;
         }
 
@@ -600,20 +713,24 @@ __device__ __forceinline__ bool flow_strip(cdesc &d, const PbTile &te, int k, in
         cL = nL; cC = nC; cR = nR;
         p2L = p1L; p2C = p1C; p2R = p1R;
         p1L = psL; p1C = psi; p1R = psR;
+        if constexpr (MODE == PB_MODE_READ) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) fp[i] = f[i];
-        rho_p = rho; jx_p = jx; jy_p = jy; bad_p = bad_r;
+            for (int i = 0; i < 9; ++i) fp[i] = f[i];
+        }
+        mo_p = mo;
+        bad_p = bad_r;
     }
     return bad;
 }
 
 template <typename FT, int H, int UNR, int MODE>
-__global__ __launch_bounds__(64) void k_flow_sweep(const PbDesc *const *__restrict__ dps,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_flow_sweep(const PbDesc *const *__restrict__ dps,
                                                     const PbTile *__restrict__ tiles, int ntiles, int k) {
     for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
         const PbTile te = tiles[tl];
         cdesc &d = *(const PbDesc PB_CAS *)dps[te.dom];
-        const bool in = !(d.flags & F_PERY) && te.y0 >= 2 && te.y0 + H + 1 < d.nyf;
+        const bool in = !(d.flags & F_PERY) && te.y0 >= 2 && te.y0 + H + 1 < d.nyf &&
+                        arena_span<FT>(d) < (1ull << 32);
         const bool nf = in ? flow_strip<FT, H, UNR, MODE, true>(d, te, k, threadIdx.x)
                            : flow_strip<FT, H, UNR, MODE, false>(d, te, k, threadIdx.x);
         if (nf) flag_error(d);
