@@ -78,11 +78,9 @@ typedef struct pb_config {
                                         heat-flux sampling needs ny_solid >= 3 */
     int32_t precision;               /* PB_FP64 or PB_FP32_DEV                   */
     uint32_t flags;                  /* PB_* flags                               */
-    int32_t tile_x, tile_y;          /* flow-kernel launch shape; 0,0 = default:  */
-                                     /* blocks of 64x4, 64x8, 32x8, 128x4, 32x16, */
-                                     /* 64x16 nodes, or column sweeps of 60       */
-                                     /* columns x 8, 16 or 32 rows (tile_x = 60); */
-                                     /* every shape gives the same bits          */
+    int32_t tile_x, tile_y;          /* flow-kernel tile: 64x4, 64x8, 32x8,       */
+                                     /* 128x4, 32x16 or 64x16 nodes; 0,0 = 64x8;  */
+                                     /* every tile gives the same bits           */
     int32_t thermal_tile;            /* thermal-kernel tile variant; 0 = default */
     double a, b, R, omega, Tc;       /* Eq. 13 (Tc explicit)                     */
     double G;                        /* Eq. 11-12 interaction strength (< 0)     */

@@ -13,7 +13,7 @@ import os
 from . import poolboil as pb
 from . import presets
 
-FLOW_TILES = [(64, 4), (64, 8), (32, 8), (128, 4), (32, 16), (64, 16), (60, 8), (60, 16), (60, 32)]
+FLOW_TILES = [(64, 4), (64, 8), (32, 8), (128, 4), (32, 16), (64, 16)]
 THERMAL_VARIANTS = list(range(4))
 CACHE = os.environ.get("POOLBOIL_TUNE_CACHE", os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                             "tune_cache.json"))

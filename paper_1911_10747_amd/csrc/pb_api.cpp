@@ -44,7 +44,7 @@ const int kEYh[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 const int kOPPh[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
 int flow_variant_of(const pb_config &c) {
-    if (c.tile_x == 0 && c.tile_y == 0) return 0;
+    if (c.tile_x == 0 && c.tile_y == 0) return 1;   // 64x8
     for (int v = 0; v < pb_flow_variants(); ++v) {
         int bx, by;
         pb_flow_tile_shape(v, &bx, &by);

@@ -161,7 +161,7 @@ __device__ __forceinline__ FT encode_pop(int i, double fs, double rho) {
         return fs;
 }
 
-// Where a node's outputs go: through global pointers at element offset oidx...
+// Where a node's outputs go: global pointers at element offset oidx.
 template <typename FT>
 struct GlobalStore {
     FT PB_GAS *f;
@@ -177,40 +177,6 @@ struct GlobalStore {
     }
 };
 
-// ...or through buffer resources: a per-lane column byte offset (vf for FT
-// arrays, vd for FP64 ones) plus a uniform row byte offset (sf, sd).
-typedef unsigned int pb_u32x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
-}
-template <typename T>
-__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    if constexpr (sizeof(T) == 4)
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-    else
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-}
-template <typename T>
-__device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    if constexpr (sizeof(T) == 4)
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, 0);
-    else
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(pb_u32x2, v), r, voff, soff, 0);
-}
-template <typename FT>
-struct BufferStore {
-    __amdgpu_buffer_rsrc_t rs;          // one resource over the domain's arrays
-    uint32_t of, orho, ovx, ovy;        // array byte offsets from its base
-    uint32_t vf, vd, sf, sd, plane_bytes;
-    __device__ __forceinline__ void pop(int i, FT v) const {
-        buf_store<FT>(v, rs, vf, of + sf + (uint32_t)i * plane_bytes);
-    }
-    __device__ __forceinline__ void fields(double r, FT ux, FT uy) const {
-        buf_store<double>(r, rs, vd, orho + sd);
-        buf_store<FT>(ux, rs, vf, ovx + sf);
-        buf_store<FT>(uy, rs, vf, ovy + sf);
-    }
-};
 
 // Lane exchange with DPP wave shifts (a VALU move, no LDS round trip): wave_shr:1
 // gives lane i the value of lane i-1 (column x-1), wave_shl:1 that of lane i+1.
@@ -261,10 +227,10 @@ __device__ __forceinline__ Mom node_moments(const double f[9]) {
 // read mode, the pulled state).  Returns true if the node is not finite.
 // Every flow kernel updates its nodes through this one function, so a node
 // gives the same bits whatever the launch shape.
-template <typename FT, int MODE, typename ST>
+template <typename FT, int MODE>
 __device__ __forceinline__ bool node_update(cdesc &d, const double f[9], const Mom &mo, double psi,
                                             const double pn[9], const double gw[9], uint32_t wmask, uint32_t oidx,
-                                            const ST &st) {
+                                            const GlobalStore<FT> &st) {
     const double rho = mo.rho, jx = mo.jx, jy = mo.jy;
     const bool frozen = (d.flags & F_FROZEN) != 0;
     const uint32_t plane = (uint32_t)d.nyf * (uint32_t)d.pitch;
@@ -500,240 +466,6 @@ __global__ __launch_bounds__(BX *BY) void k_flow(const PbDesc *const *__restrict
         __syncthreads();
         if (threadIdx.x == 0 && s_bad) flag_error(d);
         __syncthreads();
-    }
-}
-
-// ------------------------------------------------------- flow step (sweep)
-// Column-sweep form of the same step.  One wavefront owns 64 consecutive
-// columns (the middle 60 are written; two on each side are halo) and walks up
-// a strip of H fluid rows.  At row r it pulls the populations (Eq. 8) and
-// forms rho, j and psi there, then updates row r-1, whose psi neighbours
-// (rows r-2..r) are in registers and whose x-neighbours come from the
-// adjacent lanes; the loads of row r+1 are in flight meanwhile.  No LDS, no
-// barriers, and every population row is read once per strip.
-
-// pulled-state inputs of one row: the nine stored values, T(t-1) of the row
-// and, for the FP32 decode, rho(t-1) of the row above
-// Lowest address and byte span of the arrays a flow step touches.
-__device__ __forceinline__ const char *arena_lo(cdesc &d) {
-    const char *p[8] = {(const char *)d.f[0], (const char *)d.f[1], (const char *)d.rho[0], (const char *)d.rho[1],
-                        (const char *)d.vx, (const char *)d.vy, (const char *)d.T[0], (const char *)d.T[1]};
-    const char *lo = p[0];
-#pragma unroll
-    for (int i = 1; i < 8; ++i) lo = p[i] < lo ? p[i] : lo;
-    return lo;
-}
-template <typename FT>
-__device__ __forceinline__ uint64_t arena_span(cdesc &d) {
-    const uint64_t plane = (uint64_t)d.nyf * (uint64_t)d.pitch, tp = (uint64_t)d.nr * (uint64_t)d.pitch;
-    const char *lo = arena_lo(d);
-    const char *e[8] = {(const char *)d.f[0] + 9 * plane * sizeof(FT), (const char *)d.f[1] + 9 * plane * sizeof(FT),
-                        (const char *)d.rho[0] + plane * 8, (const char *)d.rho[1] + plane * 8,
-                        (const char *)d.vx + plane * sizeof(FT), (const char *)d.vy + plane * sizeof(FT),
-                        (const char *)d.T[0] + tp * 8, (const char *)d.T[1] + tp * 8};
-    const char *hi = e[0];
-#pragma unroll
-    for (int i = 1; i < 8; ++i) hi = e[i] > hi ? e[i] : hi;
-    return (uint64_t)(hi - lo);
-}
-
-template <typename FT>
-struct SweepRow {
-    FT v[9];
-    double T, rn;
-};
-
-// IN: the strip and its halo rows (y0 - 2 .. y0 + H + 1) lie inside a walled
-// fluid, so no row wraps, bounces back or sees a wall.
-template <typename FT, int H, int UNR, int MODE, bool IN>
-__device__ __forceinline__ bool flow_strip(cdesc &d, const PbTile &te, int k, int lane) {
-    constexpr bool F32 = std::is_same<FT, float>::value;
-    const bool pery = !IN && (d.flags & F_PERY) != 0;
-    const int nx = d.nx, nyf = d.nyf;
-    const int pin = (int)((d.par0 + k) & 1), pout = pin ^ 1;
-    const FT PB_GAS *fin = gcast<FT>(d.f[pin]);
-    const double PB_GAS *rin = gcast<double>(d.rho[pin]);
-    const double PB_GAS *Tt = gcast<double>(d.T[pin]);
-    const uint32_t pitch = (uint32_t)d.pitch, plane = (uint32_t)nyf * pitch;
-    const uint32_t toff = (uint32_t)d.nys * pitch;           // fluid row 0 in the T array
-    // lanes map to consecutive columns modulo nx (any nx >= 1)
-    int xg = (te.x0 - 2 + lane) % nx;
-    if (xg < 0) xg += nx;
-    const int xm = xg == 0 ? nx - 1 : xg - 1, xp = xg == nx - 1 ? 0 : xg + 1;
-    const bool out_lane = lane >= 2 && lane < 62 && te.x0 + lane - 2 < nx;
-
-    // row r as stored (wrapped when periodic); false outside a walled fluid
-    auto row_of = [&](int r, int &rr) -> bool {
-        rr = r;
-        if (IN) return true;
-        if (pery) {
-            rr %= nyf;
-            if (rr < 0) rr += nyf;
-            return true;
-        }
-        return r >= 0 && r < nyf;
-    };
-    // Interior strips address through one buffer resource over the domain's
-    // arrays: uniform array and row byte offsets in scalar registers, fixed
-    // per-lane column offsets (the caller has checked that the arrays span
-    // less than 2^32 bytes from the lowest of them).
-    constexpr uint32_t ES = sizeof(FT);
-    const char *lo = arena_lo(d);
-    const __amdgpu_buffer_rsrc_t rs = make_rsrc(lo, 0xFFFFFFFFu);
-    auto off = [&](const void *p) -> uint32_t { return (uint32_t)((const char *)p - lo); };
-    const uint32_t ofi = off(d.f[pin]), ori = off(d.rho[pin]), oTi = off(d.T[pin]);
-    const uint32_t cg = (uint32_t)xg * ES, cm = (uint32_t)xm * ES, cp = (uint32_t)xp * ES, cd = (uint32_t)xg * 8u;
-    auto load_row = [&](int r, SweepRow<FT> &p) {
-        int rr;
-        if constexpr (IN) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i)
-                p.v[i] = buf_load<FT>(rs, kEX[i] > 0 ? cm : (kEX[i] < 0 ? cp : cg),
-                                      ofi + ((uint32_t)i * plane + (uint32_t)(r - kEY[i]) * pitch) * ES);
-            p.T = buf_load<double>(rs, cd, oTi + (toff + (uint32_t)r * pitch) * 8u);
-            if constexpr (F32) p.rn = buf_load<double>(rs, cd, ori + (uint32_t)(r + 1) * pitch * 8u);
-            return;
-        }
-        if constexpr (F32) p.rn = row_of(r + 1, rr) ? rin[(uint32_t)rr * pitch + (uint32_t)xg] : 0.0;
-        if (!row_of(r, rr)) return;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            int ys = rr - kEY[i], xs = kEX[i] > 0 ? xm : (kEX[i] < 0 ? xp : xg), ii = i;
-            if (IN) {
-            } else if (pery) {
-                ys = wrap_once(ys, nyf);
-            } else if (ys < 0 || ys >= nyf) {        // halfway bounce-back
-                ii = kOPP[i];
-                xs = xg;
-                ys = rr;
-            }
-            p.v[i] = (fin + (uint32_t)ii * plane)[(uint32_t)ys * pitch + (uint32_t)xs];
-        }
-        p.T = Tt[toff + (uint32_t)rr * pitch + (uint32_t)xg];
-    };
-
-    // rho(t-1) of rows r-1 (m*), r (c*) at columns x-1 (L), x, x+1 (R)
-    double mL = 0.0, mC = 0.0, mR = 0.0, cL = 0.0, cC = 0.0, cR = 0.0;
-    // psi of rows r-1 (p1*) and r-2 (p2*)
-    double p1L = 0.0, p1C = 0.0, p1R = 0.0, p2L = 0.0, p2C = 0.0, p2R = 0.0;
-    // pulled state of row r-1 (the populations themselves only in read mode)
-    double fp[9];
-    Mom mo_p{};
-    bool bad_p = false, bad = false;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) fp[i] = 0.0;
-
-    const int r0 = te.y0 - 1;
-    if constexpr (F32) {
-        int rr;
-        if (row_of(r0 - 1, rr)) mC = rin[(uint32_t)rr * pitch + (uint32_t)xg];
-        if (row_of(r0, rr)) cC = rin[(uint32_t)rr * pitch + (uint32_t)xg];
-        mL = from_left(mC); mR = from_right(mC);
-        cL = from_left(cC); cR = from_right(cC);
-    }
-    SweepRow<FT> nxt{};
-    load_row(r0, nxt);
-#pragma unroll UNR
-    for (int j = 0; j < H + 2; ++j) {
-        const int r = r0 + j;
-        const SweepRow<FT> cur = nxt;
-        if (j + 1 < H + 2) load_row(r + 1, nxt);
-
-        // rho(t-1) of row r+1
-        double nC = 0.0, nL = 0.0, nR = 0.0;
-        if constexpr (F32) {
-            nC = cur.rn;
-            nL = from_left(nC);
-            nR = from_right(nC);
-        }
-        // pull of row r: decode, moments, psi
-        int rr;
-        const bool live = row_of(r, rr);
-        double f[9], psi = 0.0;
-        Mom mo{};
-        bool bad_r = false;
-        if (live) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                if constexpr (F32) {
-                    const int ys = rr - kEY[i];
-                    const bool bb = !IN && !pery && (ys < 0 || ys >= nyf);
-                    double rs;
-                    if (bb) rs = cC;
-                    else if (kEY[i] > 0) rs = kEX[i] > 0 ? mL : (kEX[i] < 0 ? mR : mC);
-                    else if (kEY[i] < 0) rs = kEX[i] > 0 ? nL : (kEX[i] < 0 ? nR : nC);
-                    else rs = kEX[i] > 0 ? cL : (kEX[i] < 0 ? cR : cC);
-                    f[i] = kW[i] * rs + (double)cur.v[i];
-                } else {
-                    f[i] = cur.v[i];
-                }
-            }
-            mo = node_moments(f);
-            psi = eos_psi(d, mo.rho, cur.T, bad_r);
-        } else {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) f[i] = 0.0;
-        }
-        const double psL = from_left(psi), psR = from_right(psi);
-
-        // update of row q = r-1 (psi rows r-2, r-1, r)
-        const int q = r - 1;
-        if (j >= 2 && (IN || q < nyf) && out_lane) {
-            double pn[9], gw[9];
-            uint32_t wmask = 0;
-#pragma unroll
-            for (int i = 1; i < 9; ++i) {
-                if (kEY[i] > 0) pn[i] = kEX[i] > 0 ? psR : (kEX[i] < 0 ? psL : psi);
-                else if (kEY[i] < 0) pn[i] = kEX[i] > 0 ? p2R : (kEX[i] < 0 ? p2L : p2C);
-                else pn[i] = kEX[i] > 0 ? p1R : (kEX[i] < 0 ? p1L : p1C);
-                gw[i] = 0.0;
-                const int yn = q + kEY[i];
-                if (!IN && !pery && (yn < 0 || yn >= nyf)) {
-                    const int xn = kEX[i] > 0 ? xp : (kEX[i] < 0 ? xm : xg);
-                    gw[i] = (yn < 0) ? d.gbot[xn] : d.gtop[xn];
-                    wmask |= 1u << i;
-                }
-            }
-            const uint32_t oidx = (uint32_t)q * pitch + (uint32_t)xg;
-            bool nf;
-            if constexpr (IN && MODE == PB_MODE_STEP) {
-                const BufferStore<FT> st{rs, off(d.f[pout]), off(d.rho[pout]), off(d.vx), off(d.vy),
-                                         cg, cd, (uint32_t)q * pitch * ES, (uint32_t)q * pitch * 8u, plane * ES};
-                nf = node_update<FT, MODE>(d, fp, mo_p, p1C, pn, gw, wmask, oidx, st);
-            } else {
-                const GlobalStore<FT> st{gcast_w<FT>(d.f[pout]), gcast_w<double>(d.rho[pout]), gcast_w<FT>(d.vx),
-                                         gcast_w<FT>(d.vy), plane, oidx};
-                nf = node_update<FT, MODE>(d, fp, mo_p, p1C, pn, gw, wmask, oidx, st);
-            }
-            bad = bad || nf || bad_p;
-        }
-
-        // shift the windows by one row
-        mL = cL; mC = cC; mR = cR;
-        cL = nL; cC = nC; cR = nR;
-        p2L = p1L; p2C = p1C; p2R = p1R;
-        p1L = psL; p1C = psi; p1R = psR;
-        if constexpr (MODE == PB_MODE_READ) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) fp[i] = f[i];
-        }
-        mo_p = mo;
-        bad_p = bad_r;
-    }
-    return bad;
-}
-
-template <typename FT, int H, int UNR, int MODE>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_flow_sweep(const PbDesc *const *__restrict__ dps,
-                                                    const PbTile *__restrict__ tiles, int ntiles, int k) {
-    for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
-        const PbTile te = tiles[tl];
-        cdesc &d = *(const PbDesc PB_CAS *)dps[te.dom];
-        const bool in = !(d.flags & F_PERY) && te.y0 >= 2 && te.y0 + H + 1 < d.nyf &&
-                        arena_span<FT>(d) < (1ull << 32);
-        const bool nf = in ? flow_strip<FT, H, UNR, MODE, true>(d, te, k, threadIdx.x)
-                           : flow_strip<FT, H, UNR, MODE, false>(d, te, k, threadIdx.x);
-        if (nf) flag_error(d);
     }
 }
 
@@ -1089,10 +821,8 @@ __global__ void k_advance(PbDesc *const *__restrict__ dps, int ndom, int nsteps)
 
 // ------------------------------------------------------------ launch helpers
 // Flow tile variants: (BX, BY) with BX * BY threads per block.
-// tiles of BX x BY nodes (one block of BX * BY threads each), then column
-// sweeps of 60 written columns x H rows (one wavefront each)
-static const int kFlowShapes[][2] = {{64, 4}, {64, 8}, {32, 8}, {128, 4}, {32, 16}, {64, 16},
-                                     {60, 8}, {60, 16}, {60, 32}};
+// tiles of BX x BY nodes, one block of BX * BY threads each
+static const int kFlowShapes[][2] = {{64, 4}, {64, 8}, {32, 8}, {128, 4}, {32, 16}, {64, 16}};
 // column sweeps of 56 written columns x H rows
 // the whole strip is unrolled so the operator ring lives in registers
 static const int kThermalShapes[][2] = {{56, 28}, {56, 20}, {56, 24}, {56, 16}};
@@ -1123,14 +853,6 @@ static hipError_t launch_flow_t(int variant, const PbDesc *const *dps, const PbT
         PB_FLOW_CASE(4, 32, 16)
         PB_FLOW_CASE(5, 64, 16)
 #undef PB_FLOW_CASE
-#define PB_SWEEP_CASE(V, H, UNR)                                                                       \
-    case V:                                                                                           \
-        hipLaunchKernelGGL((k_flow_sweep<FT, H, UNR, MODE>), dim3(grid), dim3(64), 0, s, dps, t, nt, k); \
-        break;
-        PB_SWEEP_CASE(6, 8, 10)
-        PB_SWEEP_CASE(7, 16, 18)
-        PB_SWEEP_CASE(8, 32, 2)
-#undef PB_SWEEP_CASE
         default:
             return hipErrorInvalidValue;
     }

@@ -25,11 +25,7 @@ def _report(name, errs):
     print(name, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
 
 
-# default tiles (64x4 blocks) and a column sweep of 60 columns x 16 rows
-FLOW_FAMILIES = [(0, 0), (60, 16)]
-
-
-@pytest.mark.parametrize("tile", FLOW_FAMILIES)
+@pytest.mark.parametrize("tile", [(0, 0), (64, 4)])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_pool_boiling_100x100_200_steps(precision, tile):
     """Plain pool boiling, 100x100 fluid over a 100x10 heater, liquid below
@@ -50,7 +46,7 @@ def test_ragged_domain_and_tile_shapes_are_bit_identical():
     every thermal variant."""
     P, d, bc, rho, T = pool_case(77, 45, 5, superheat=0.2, n_spots=3, seed=7, y0=17)
     ref = None
-    shapes = [(64, 4), (64, 8), (32, 8), (128, 4), (32, 16), (64, 16), (60, 8), (60, 16), (60, 32), (64, 4)]
+    shapes = [(64, 4), (64, 8), (32, 8), (128, 4), (32, 16), (64, 16), (64, 4)]
     for i, tile in enumerate(shapes):
         g = gpu_domain(P, bc, rho, T, 0, tile=tile, thermal_tile=i % 4)
         g.step(120)
@@ -69,7 +65,7 @@ def test_ragged_domain_and_tile_shapes_are_bit_identical():
                 np.testing.assert_array_equal(r[k], ref[k], err_msg=f"{k} differs for tile {tile}")
 
 
-@pytest.mark.parametrize("tile", [(0, 0), (60, 8)])
+@pytest.mark.parametrize("tile", [(0, 0), (32, 16)])
 @pytest.mark.parametrize("isothermal", [1, 0])
 def test_periodic_drop(isothermal, tile):
     """Fully periodic box with a drop (no walls, no heater): exercises the
@@ -100,7 +96,7 @@ def test_frozen_flow_conduction():
     assert g["flux"]["q_bottom_mean"] == pytest.approx(o["flux"]["q_bottom_mean"], rel=1e-11)
 
 
-@pytest.mark.parametrize("tile", [(0, 0), (60, 8)])
+@pytest.mark.parametrize("tile", [(0, 0), (32, 16)])
 @pytest.mark.parametrize("shape", [(1, 1, 3), (2, 3, 3), (3, 70, 4), (130, 2, 3)])
 def test_degenerate_shapes(shape, tile):
     """Single column, two-row fluid, tall-thin and wide-flat domains."""
