@@ -489,16 +489,23 @@ struct Coef9 {
 };
 
 
-// harmonic-mean link conductance; a negative value marks the T_top row, whose
-// links take the conductance of the other node
-// (FL: both conductances are fluid ones, positive in any physical state)
+// Harmonic-mean link conductance 2ab/(a+b) in two halves around a shared
+// reciprocal: the divisor to invert (1 where none is needed) and the link
+// from the inverted sum.  A negative value marks the T_top row, whose links
+// take the conductance of the other node; a zero sum gives a zero link.  FL:
+// both conductances are fluid ones, positive in any physical state.
 template <bool FL>
-__device__ __forceinline__ double hlink(double a, double b) {
-    if constexpr (FL) return 2.0 * a * b * frcp(a + b);
+__device__ __forceinline__ double hlink_div(double a, double b, double s) {
+    if constexpr (FL) return s;
+    return (a < 0.0 || b < 0.0 || !(s > 0.0)) ? 1.0 : s;
+}
+template <bool FL>
+__device__ __forceinline__ double hlink_sel(double a, double b, double s, double inv_s) {
+    const double h = 2.0 * a * b * inv_s;
+    if constexpr (FL) return h;
     if (a < 0.0) return b;
     if (b < 0.0) return a;
-    const double s = a + b;
-    return s > 0.0 ? 2.0 * a * b * frcp(s) : 0.0;
+    return s > 0.0 ? h : 0.0;
 }
 
 struct RowIn {
@@ -616,8 +623,32 @@ __device__ __forceinline__ void thermal_strip(cdesc &d, const PbTile &te, int k,
         const double p = cur.vx + cur.vy, m = cur.vx - cur.vy;
 
         // operator of row a = n-1
-        const double lE = hlink<FL>(lam_1, lamR_1), lN = hlink<FL>(lam_1, cur.lam);
-        const double lNE = hlink<FL>(lam_1, lamR), lNW = hlink<FL>(lam_1, lamL);
+        // The row's six divisions share one reciprocal (product chain and
+        // back-substitution, Montgomery's batch inversion): the four link
+        // sums of the harmonic means, rho C_V, and the two Peng-Robinson
+        // denominators (1 - b rho)(1 + 2 b rho - b^2 rho^2) of (dP/dT)_rho.
+        // A divisor that is not used (link special case, non-fluid row) is
+        // replaced by 1.
+        const double sE = lam_1 + lamR_1, sN = lam_1 + cur.lam, sNE = lam_1 + lamR, sNW = lam_1 + lamL;
+        const bool fluid_1 = FL || kind_1 == KIND_FLUID;
+        const double br = d.b * rho_1;
+        const double q1 = 1.0 - br, q2 = 1.0 + 2.0 * br - br * br;
+        const double dE = hlink_div<FL>(lam_1, lamR_1, sE), dN = hlink_div<FL>(lam_1, cur.lam, sN);
+        const double dNE = hlink_div<FL>(lam_1, lamR, sNE), dNW = hlink_div<FL>(lam_1, lamL, sNW);
+        const double dC = fluid_1 ? rho_1 * d.Cv : 1.0, dAB = fluid_1 ? q1 * q2 : 1.0;
+        const double p1 = dE * dN, p2 = p1 * dNE, p3 = p2 * dNW, p4 = p3 * dC, p5 = p4 * dAB;
+        double rr = frcp(p5);
+        const double iAB = rr * p4;
+        rr = rr * dAB;
+        const double iC = rr * p3;
+        rr = rr * dC;
+        const double iNW = rr * p2;
+        rr = rr * dNW;
+        const double iNE = rr * p1;
+        rr = rr * dNE;
+        const double iN = rr * dE, iE = rr * dN;
+        const double lE = hlink_sel<FL>(lam_1, lamR_1, sE, iE), lN = hlink_sel<FL>(lam_1, cur.lam, sN, iN);
+        const double lNE = hlink_sel<FL>(lam_1, lamR, sNE, iNE), lNW = hlink_sel<FL>(lam_1, lamL, sNW, iNW);
         const double lW = from_left(lE);
         // Eq. 27 on v (v = 0 outside the fluid): 3 sum_i w_i e_i . v(x + e_i),
         // grouped as U(x+1) - V(x-1) + (vy(above) - vy(below)) / 9
@@ -626,18 +657,16 @@ __device__ __forceinline__ void thermal_strip(cdesc &d, const PbTile &te, int k,
         const double UR = from_right(U), VL = from_left(V);
         Coef9 cf{};
         if (FL || kind_1 == KIND_FLUID || kind_1 == KIND_SOLID) {
-            double C1;
-            if (FL || kind_1 == KIND_FLUID) C1 = frcp(rho_1 * d.Cv); else C1 = c1_solid;
+            const double C1 = fluid_1 ? iC : c1_solid;
             const double c1 = W1 * C1 * lE, c2 = W1 * C1 * lN, c3 = W1 * C1 * lW, c4 = W1 * C1 * lN_2;
             const double c5 = W2 * C1 * lNE, c6 = W2 * C1 * lNW, c7 = W2 * C1 * lNEL_2, c8 = W2 * C1 * lNWR_2;
             cf.k0 = -(((c1 + c2) + (c3 + c4)) + ((c5 + c6) + (c7 + c8)));
             cf.k1 = c1; cf.k2 = c2; cf.k3 = c3; cf.k4 = c4;
             cf.k5 = c5; cf.k6 = c6; cf.k7 = c7; cf.k8 = c8;
-            if (FL || kind_1 == KIND_FLUID) {
+            if (fluid_1) {
                 const double divv = 3.0 * ((UR - VL) + (1.0 / 9.0) * (cur.vy - vy_2));
-                const double br = d.b * rho_1;
-                const double A = rho_1 * d.R * frcp(1.0 - br);
-                const double B = d.a * d.kappa * rho_1 * rho_1 * frcp(1.0 + 2.0 * br - br * br);
+                const double A = rho_1 * d.R * q2 * iAB;                     // rho R / (1 - b rho)
+                const double B = d.a * d.kappa * rho_1 * rho_1 * q1 * iAB;   // a kappa rho^2 / (1 + 2 b rho - b^2 rho^2)
                 const double AL = -C1 * divv * A, BE = -C1 * divv * B;
                 cf.k0 += AL - BE * lat_a;
                 cf.beta = BE * lat_b;
