@@ -75,7 +75,8 @@ enum { PB_FP64 = 0, PB_FP32_DEV = 1 };
  * density) and per-step invariants from it. */
 typedef struct pb_config {
     int32_t nx, ny_fluid, ny_solid;  /* ny_solid >= 1 unless PB_PERIODIC_Y (then 0);
-                                        heat-flux sampling needs ny_solid >= 3 */
+                                        ny_solid = 1 is model A of Section 4.1
+                                        (the Dirichlet row under the fluid)   */
     int32_t precision;               /* PB_FP64 or PB_FP32_DEV                   */
     uint32_t flags;                  /* PB_* flags                               */
     int32_t tile_x, tile_y;          /* flow-kernel tile: 64x4, 64x8, 32x8,       */
@@ -105,10 +106,11 @@ typedef struct pb_bc {
 
 /* Heat flux (lattice units).  q_bottom: -lambda_S dT/dy at the heater bottom
  * with the one-sided second-order difference of Eq. 36 (the quantity of
- * Eq. 39 before scaling), averaged over x.  q_top: conductive link flux from
- * the heater top row into the fluid, averaged over x (uses the conductances
- * of the last completed step).  T_w: mean heater-top temperature (Section
- * 3.2).  *_mean: averages over the samples of the window (Eq. 38). */
+ * Eq. 39 before scaling), averaged over x; with ny_solid < 3 (model A) there
+ * are no heater rows to difference and q_bottom = q_top.  q_top: conductive
+ * link flux from the heater top row into the fluid, averaged over x (uses the
+ * conductances of the last completed step).  T_w: mean heater-top temperature
+ * (Section 3.2).  *_mean: averages over the samples of the window (Eq. 38). */
 typedef struct pb_flux {
     double q_bottom_inst, q_top_inst, T_w_inst;
     double q_bottom_mean, q_top_mean, T_w_mean;

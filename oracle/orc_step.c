@@ -436,13 +436,18 @@ static void collide_and_stream(orc_dom *d) {
             }
 }
 
-/* Eq. 36 at the heater bottom (Eq. 39), link flux and mean T at the heater top. */
+/* Eq. 36 at the heater bottom (Eq. 39), link flux and mean T at the heater top.
+ * With fewer than three heater rows (model A of Section 4.1 has none: the
+ * Dirichlet row sits directly under the fluid) Eq. 36 has no heater rows to
+ * difference, and the bottom flux is the link flux into the fluid. */
 static void sample_flux(orc_dom *d) {
     const orc_params *p = &d->p;
     double sb = 0.0, st = 0.0, sw = 0.0;
-    for (int x = 0; x < d->nx; ++x) {
-        double dTdy = (4.0 * d->T[NI(d, 1, x)] - d->T[NI(d, 2, x)] - 3.0 * d->T[NI(d, 0, x)]) / 2.0;
-        sb += -p->lambda_S * dTdy;
+    if (d->nys >= 3) {
+        for (int x = 0; x < d->nx; ++x) {
+            double dTdy = (4.0 * d->T[NI(d, 1, x)] - d->T[NI(d, 2, x)] - 3.0 * d->T[NI(d, 0, x)]) / 2.0;
+            sb += -p->lambda_S * dTdy;
+        }
     }
     int r = d->nys - 1;
     for (int x = 0; x < d->nx; ++x) {
@@ -462,8 +467,8 @@ static void sample_flux(orc_dom *d) {
         st += -6.0 * link;
         sw += d->T[NI(d, r, x)];
     }
-    d->q_bot_inst = sb / d->nx;
     d->q_top_inst = st / d->nx;
+    d->q_bot_inst = d->nys >= 3 ? sb / d->nx : d->q_top_inst;
     d->Tw_inst = sw / d->nx;
     d->q_bot_sum += d->q_bot_inst; d->q_top_sum += d->q_top_inst; d->Tw_sum += d->Tw_inst;
     d->n_samples += 1;
@@ -500,7 +505,7 @@ static void one_step(orc_dom *d) {
     if (!p->isothermal) thermal_rk4(d, d->ux, d->uy);
     if (!p->frozen_flow) collide_and_stream(d);
     d->t += 1;
-    if (!p->periodic_y && d->nys >= 3 && d->t >= d->fl_ta && d->t < d->fl_tb &&
+    if (!p->periodic_y && d->nys >= 1 && d->t >= d->fl_ta && d->t < d->fl_tb &&
         (d->t - d->fl_ta) % d->fl_every == 0)
         sample_flux(d);
     size_t nt = (size_t)d->nx * d->nr;

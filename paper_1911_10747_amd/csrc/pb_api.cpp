@@ -233,7 +233,7 @@ int check_dom(const pb_domain *d) {
 
 int enqueue_steps(pb_domain *d, int64_t n) {
     const bool frozen = d->cfg.flags & PB_FROZEN_FLOW, iso = d->cfg.flags & PB_ISOTHERMAL;
-    const bool sampling = !(d->cfg.flags & PB_PERIODIC_Y) && d->cfg.ny_solid >= 3 && d->hd.fl_tb > d->hd.fl_ta;
+    const bool sampling = !(d->cfg.flags & PB_PERIODIC_Y) && d->cfg.ny_solid >= 1 && d->hd.fl_tb > d->hd.fl_ta;
     const PbDesc *const *dp = (const PbDesc *const *)d->dptr;
     // the descriptor's kernel step index is an int; long runs are split
     const int64_t chunk = 1 << 30;
@@ -540,8 +540,6 @@ int pb_flux_window(pb_domain *d, int64_t t_a, int64_t t_b, int32_t every) {
     int rc = check_dom(d);
     if (rc) return rc;
     if (every < 1) return fail(PB_EINVAL, "every must be >= 1");
-    if (!(d->cfg.flags & PB_PERIODIC_Y) && d->cfg.ny_solid < 3 && t_b > t_a)
-        return fail(PB_EINVAL, "heat-flux sampling needs ny_solid >= 3 (Eq. 36 uses rows 0-2)");
     PB_HIP(hipStreamSynchronize(d->stream));
     const double zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     PB_HIP(hipMemcpyAsync(d->hd.flux, zero, sizeof(zero), hipMemcpyHostToDevice, d->stream));
@@ -576,7 +574,7 @@ int pb_profile_steps(pb_domain *d, int64_t n, double *avg_ms) {
     if (!avg_ms) return fail(PB_EINVAL, "avg_ms is NULL");
     if (n < 1 || n > (1 << 20)) return fail(PB_EINVAL, "n must be in [1, 2^20]");
     const bool frozen = d->cfg.flags & PB_FROZEN_FLOW, iso = d->cfg.flags & PB_ISOTHERMAL;
-    const bool sampling = !(d->cfg.flags & PB_PERIODIC_Y) && d->cfg.ny_solid >= 3 && d->hd.fl_tb > d->hd.fl_ta;
+    const bool sampling = !(d->cfg.flags & PB_PERIODIC_Y) && d->cfg.ny_solid >= 1 && d->hd.fl_tb > d->hd.fl_ta;
     const PbDesc *const *dp = (const PbDesc *const *)d->dptr;
     const int m = (int)n;
     // events e[2k] before the flow launch of step k, e[2k+1] between flow and
@@ -727,7 +725,7 @@ int pb_batch_step(pb_batch *b, int64_t n) {
     // descriptors must match the host mirrors before device-side advancing
     b->any_flux = false;
     for (pb_domain *d : b->doms) {
-        if (d->hd.fl_tb > d->hd.fl_ta && d->cfg.ny_solid >= 3) b->any_flux = true;
+        if (d->hd.fl_tb > d->hd.fl_ta && d->cfg.ny_solid >= 1) b->any_flux = true;
     }
     int rc;
     // the batch stream starts after the work already queued on member streams

@@ -744,11 +744,14 @@ __global__ __launch_bounds__(64, WPE) void k_thermal_sweep(const PbDesc *const *
 
 // --------------------------------------------------------- heat-flux sample
 // One block per domain; fixed-order tree reduction so the result does not
-// depend on what else runs.
+// depend on what else runs.  With fewer than three heater rows (model A of
+// Section 4.1: the Dirichlet row directly under the fluid) Eq. 36 has no
+// heater rows to difference and the bottom flux is the link flux into the
+// fluid.
 __global__ __launch_bounds__(256) void k_flux(const PbDesc *const *__restrict__ dps, int k) {
     cdesc &d = *(const PbDesc PB_CAS *)dps[blockIdx.x];
     const int64_t t = d.t0 + k + 1;
-    if ((d.flags & F_PERY) || d.nys < 3 || d.nyf < 1) return;
+    if ((d.flags & F_PERY) || d.nys < 1 || d.nyf < 1) return;
     if (t < d.fl_ta || t >= d.fl_tb || ((t - d.fl_ta) % d.fl_every) != 0) return;
     const int pout = (int)((d.par0 + k + 1) & 1);
     const double PB_GAS *T = gcast<double>(d.T[pout]);
@@ -757,8 +760,10 @@ __global__ __launch_bounds__(256) void k_flux(const PbDesc *const *__restrict__ 
     double ab = 0.0, at = 0.0, aw = 0.0;
     const int r = d.nys - 1;
     for (int x = threadIdx.x; x < d.nx; x += 256) {
-        const double T0 = T[x], T1 = T[d.pitch + x], T2 = T[2 * (size_t)d.pitch + x];
-        ab += -d.lambda_S * ((4.0 * T1 - T2 - 3.0 * T0) * 0.5);           // Eq. 36
+        if (d.nys >= 3) {
+            const double T0 = T[x], T1 = T[d.pitch + x], T2 = T[2 * (size_t)d.pitch + x];
+            ab += -d.lambda_S * ((4.0 * T1 - T2 - 3.0 * T0) * 0.5);       // Eq. 36
+        }
         const double Tr = T[(size_t)r * d.pitch + x];
         double link = 0.0;
         const int xs[3] = {x, x + 1 < d.nx ? x + 1 : 0, x > 0 ? x - 1 : d.nx - 1};
@@ -786,7 +791,8 @@ __global__ __launch_bounds__(256) void k_flux(const PbDesc *const *__restrict__ 
     }
     if (threadIdx.x == 0) {
         const double inx = 1.0 / (double)d.nx;
-        const double qb = sb[0] * inx, qt = st[0] * inx, tw = sw[0] * inx;
+        const double qt = st[0] * inx, tw = sw[0] * inx;
+        const double qb = d.nys >= 3 ? sb[0] * inx : qt;
         double PB_GAS *fl = gcast_w<double>(d.flux);
         fl[0] = qb;
         fl[1] = qt;

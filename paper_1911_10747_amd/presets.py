@@ -84,7 +84,7 @@ def make_domain(spec, d=None, use_torch=True, stream=None, with_window=True):
     bc, rho, T = initial_state(spec, d)
     dom.set_bc(**bc)
     dom.set_fields(rho, T)
-    if with_window and spec.nys >= 3:
+    if with_window and spec.nys >= 1:
         # Eq. 38 time mean over the second half of the run
         dom.flux_window(spec.steps // 2, spec.steps + 1, spec.flux_every)
     return dom

@@ -97,15 +97,39 @@ def test_frozen_flow_conduction():
 
 
 @pytest.mark.parametrize("tile", [(0, 0), (32, 16)])
-@pytest.mark.parametrize("shape", [(1, 1, 3), (2, 3, 3), (3, 70, 4), (130, 2, 3)])
+@pytest.mark.parametrize("shape", [(1, 1, 3), (2, 3, 3), (3, 70, 4), (130, 2, 3), (2, 1, 1), (5, 4, 2)])
 def test_degenerate_shapes(shape, tile):
-    """Single column, two-row fluid, tall-thin and wide-flat domains."""
+    """Single column, one- and two-row fluid, tall-thin and wide-flat
+    domains, one- and two-row heaters; heat flux sampled every step."""
     nx, nyf, nys = shape
     P, d, bc, rho, T = pool_case(nx, nyf, nys, superheat=0.15, n_spots=0, y0=max(1, nyf // 2))
-    g, o = run_pair(P, bc, rho, T, steps=60, precision=0, tile=tile)
+    g, o = run_pair(P, bc, rho, T, steps=60, precision=0, tile=tile, window=(1, 61, 1))
     errs = compare(g, o)
     _report(f"shape {shape} tile={tile}", errs)
     assert all(v <= 1e-11 for v in errs.values()), errs
+    assert g["flux"]["n_samples"] == o["flux"]["n_samples"] == 60
+    for k in ("q_bottom_mean", "q_top_mean", "T_w_mean"):
+        assert g["flux"][k] == pytest.approx(o["flux"][k], rel=1e-10, abs=1e-15), k
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_model_a_with_sinusoid_trigger(precision):
+    """Model A of Section 4.1 (no heater: T_b is set on the Dirichlet row
+    directly under the fluid, ny_solid = 1) with the Section 3.2 trigger
+    T_b + 0.02 Tc sin(2 pi (x - l/4) / l) over a window of steps, then uniform
+    T_b; the fluid is 2 l wide as in the paper's domain.  200 steps against
+    the oracle; the heat flux is the link flux into the fluid."""
+    nx, nyf, lam = 96, 64, 48.0
+    P, d, bc, rho, T = pool_case(nx, nyf, 1, superheat=0.15, n_spots=0, y0=26)
+    bc = dict(bc, Tb_alt=W.sinus_Tb(nx, bc["Tb"][0], 0.02 * d["Tc"], lam), t0=30, t1=150)
+    g, o = run_pair(P, bc, rho, T, steps=200, precision=precision, window=(20, 201, 10))
+    errs = compare(g, o)
+    _report(f"model A prec={precision}", errs)
+    assert all(v <= TOL[precision] for v in errs.values()), errs
+    assert g["flux"]["n_samples"] == o["flux"]["n_samples"] == 19
+    assert g["flux"]["q_bottom_mean"] == g["flux"]["q_top_mean"]
+    for k in ("q_bottom_mean", "T_w_mean", "q_bottom_inst"):
+        assert g["flux"][k] == pytest.approx(o["flux"][k], rel=TOL[precision] * 10, abs=1e-15), k
 
 
 def test_bottom_window_and_zero_steps():

@@ -438,6 +438,35 @@ def test_steady_conduction_through_heater_and_liquid(oracle_lib):
     assert hf["T_w_inst"] == pytest.approx(prof[nys - 1], rel=1e-12)
 
 
+@pytest.mark.parametrize("nys", [1, 2])
+def test_steady_conduction_thin_heater(oracle_lib, nys):
+    """Model A (Section 4.1, Fig. 1: no heater, T_b set directly under the
+    fluid) is one heater row, the Dirichlet row itself; a single solid row
+    over it is the thinnest conjugate heater.  Steady 1-D conduction gives the
+    same series-resistance profile as above, and with fewer than three heater
+    rows the bottom heat flux is the link flux into the fluid."""
+    nx, nyf = 3, 5
+    P, d = params(nx, nyf, nys, frozen_flow=1)
+    lamL = P["Cvchi"] * d["rho_L"]
+    lamS = P["lambda_S"]
+    Tb, Tt = d["Tsat"] + 0.1 * d["Tc"], d["Tsat"]
+    dom = orc.Domain(**P)
+    dom.set_bc(Tt, np.full(nx, Tb))
+    dom.set_fields(np.full((nyf, nx), d["rho_L"]), W.thermal_init(nx, nys, nyf, Tt, np.full(nx, Tb)))
+    dom.step(40000)
+    dom.flux_window(dom.t + 1, dom.t + 3, 1)
+    dom.step(2)
+    res = [1 / lamS] * (nys - 1) + [(lamS + lamL) / (2 * lamS * lamL)] + [1 / lamL] * (nyf - 1) + [1 / lamL]
+    q = (Tb - Tt) / sum(res)
+    prof = Tb - q * np.concatenate([[0.0], np.cumsum(res)])[: nys + nyf]
+    np.testing.assert_allclose(dom.read()["T"][:, 0], prof, rtol=1e-11)
+    hf = dom.heat_flux()
+    assert hf["n_samples"] == 2
+    assert hf["q_bottom_inst"] == hf["q_top_inst"]
+    assert hf["q_bottom_mean"] == pytest.approx(q, rel=1e-9)
+    assert hf["T_w_mean"] == pytest.approx(prof[nys - 1], rel=1e-12)
+
+
 def test_bottom_temperature_window(oracle_lib):
     """Section 3.2 trigger: the alternative heater-bottom row is active for
     t0 <= t < t1 and the base row outside; Dirichlet row 0 holds T_b(x, t)."""
