@@ -169,12 +169,15 @@ double pb_rho_bar(const pb_domain *dom);          /* rho_bar of Eq. 15      */
 
 /* Batched stepping of many domains in shared launches (one flow and one
  * thermal launch per step for the whole set, tiles of every domain in one
- * work-list), optionally replayed from a captured HIP graph of
- * steps_per_graph steps.  All domains must share precision and the stream
- * given here; they are stepped in lock-step.  Per-node arithmetic does not
- * depend on the batch, so each domain's result is bit-identical to stepping
- * it alone.  persistent_blocks > 0 caps the grid (blocks then loop over the
- * work-list).  The domains must outlive the batch. */
+ * work-list; frozen-flow domains are left out of the flow launch and
+ * isothermal ones out of the thermal launch), optionally replayed from a
+ * captured HIP graph of steps_per_graph steps (even).  All domains must share
+ * the precision; they are stepped in lock-step on `stream`, or on a stream of
+ * the batch's own if it is NULL, each pb_batch_step ordered after the work
+ * already queued on the domains' streams and before work queued there later.
+ * Per-node arithmetic does not depend on the batch, so each domain's result is
+ * bit-identical to stepping it alone.  persistent_blocks > 0 caps the grid
+ * (blocks then loop over the work-list).  The domains must outlive the batch. */
 int pb_batch_create(pb_domain *const *doms, int32_t n, int32_t steps_per_graph, int32_t persistent_blocks,
                     void *stream, pb_batch **out);
 int pb_batch_step(pb_batch *batch, int64_t n);

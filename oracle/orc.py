@@ -113,7 +113,7 @@ class Domain:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and callable(lib):          # module globals are gone at interpreter exit
             lib().orc_destroy(h)
             self._h = None
 

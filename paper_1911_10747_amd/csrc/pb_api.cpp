@@ -639,8 +639,6 @@ int pb_batch_create(pb_domain *const *doms, int32_t n, int32_t steps_per_graph, 
         if (!doms[j]) return fail(PB_EINVAL, "domain %d is NULL", j);
         if (!doms[j]->fields_set) return fail(PB_ESTATE, "domain %d has no fields", j);
         if (doms[j]->cfg.precision != prec) return fail(PB_EINVAL, "mixed precisions in one batch");
-        if (doms[j]->cfg.flags & (PB_FROZEN_FLOW | PB_ISOTHERMAL))
-            return fail(PB_EINVAL, "batches step the full method (no frozen/isothermal domains)");
         for (int i = 0; i < j; ++i)
             if (doms[i] == doms[j]) return fail(PB_EINVAL, "domain listed twice");
     }
@@ -660,9 +658,12 @@ int pb_batch_create(pb_domain *const *doms, int32_t n, int32_t steps_per_graph, 
     int fbx, fby, tbx, tby;
     pb_flow_tile_shape(b->fvar, &fbx, &fby);
     pb_thermal_tile_shape(b->tvar, &tbx, &tby);
+    // a launch's work-list holds the tiles of the domains that take that part
+    // of the step (frozen-flow domains skip the flow, isothermal ones the
+    // energy equation, as when stepped alone)
     for (int j = 0; j < n; ++j) {
-        make_tiles(tf, j, doms[j]->cfg.nx, doms[j]->cfg.ny_fluid, fbx, fby);
-        make_tiles(tt, j, doms[j]->cfg.nx, doms[j]->nr, tbx, tby);
+        if (!(doms[j]->cfg.flags & PB_FROZEN_FLOW)) make_tiles(tf, j, doms[j]->cfg.nx, doms[j]->cfg.ny_fluid, fbx, fby);
+        if (!(doms[j]->cfg.flags & PB_ISOTHERMAL)) make_tiles(tt, j, doms[j]->cfg.nx, doms[j]->nr, tbx, tby);
         ptrs[j] = doms[j]->ddesc;
     }
     b->nt_flow = (int)tf.size();
@@ -694,8 +695,8 @@ int pb_batch_create(pb_domain *const *doms, int32_t n, int32_t steps_per_graph, 
         hipEventCreateWithFlags(&b->ev_dom, hipEventDisableTiming) != hipSuccess)
         return bad(fail(PB_EDEVICE, "event creation failed"));
     if (hipMalloc((void **)&b->dptrs, n * sizeof(void *)) != hipSuccess ||
-        hipMalloc((void **)&b->dtiles_flow, tf.size() * sizeof(PbTile)) != hipSuccess ||
-        hipMalloc((void **)&b->dtiles_th, tt.size() * sizeof(PbTile)) != hipSuccess)
+        hipMalloc((void **)&b->dtiles_flow, std::max<size_t>(1, tf.size()) * sizeof(PbTile)) != hipSuccess ||
+        hipMalloc((void **)&b->dtiles_th, std::max<size_t>(1, tt.size()) * sizeof(PbTile)) != hipSuccess)
         return bad(fail(PB_ENOMEM, "batch tables allocation failed"));
     for (int j = 0; j < n; ++j)
         if (hipStreamSynchronize(doms[j]->stream) != hipSuccess) return bad(fail(PB_EDEVICE, "sync failed"));
@@ -711,8 +712,11 @@ static int batch_enqueue(pb_batch *b, int nsteps) {
     const PbDesc *const *dp = (const PbDesc *const *)b->dptrs;
     const int nd = (int)b->doms.size();
     for (int k = 0; k < nsteps; ++k) {
-        PB_HIP(pb_launch_flow(b->prec, PB_MODE_STEP, b->fvar, dp, b->dtiles_flow, b->nt_flow, b->grid_flow, k, b->stream));
-        PB_HIP(pb_launch_thermal(b->prec, b->tvar, dp, b->dtiles_th, b->nt_th, b->grid_th, k, b->stream));
+        if (b->nt_flow > 0)
+            PB_HIP(pb_launch_flow(b->prec, PB_MODE_STEP, b->fvar, dp, b->dtiles_flow, b->nt_flow, b->grid_flow, k,
+                                  b->stream));
+        if (b->nt_th > 0)
+            PB_HIP(pb_launch_thermal(b->prec, b->tvar, dp, b->dtiles_th, b->nt_th, b->grid_th, k, b->stream));
         if (b->any_flux) PB_HIP(pb_launch_flux(dp, nd, k, b->stream));
     }
     PB_HIP(pb_launch_advance(b->dptrs, nd, nsteps, b->stream));

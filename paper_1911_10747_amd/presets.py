@@ -35,6 +35,25 @@ def derived(a=None, b=None, R=None, omega=None, G=-1.0, t_ratio=W.T_SAT_OVER_TC)
     return Derived(Tc, Ts, rl, rv, pb.eos_psi(a, b, R, omega, Tc, G, rl, Ts), pb.eos_psi(a, b, R, omega, Tc, G, rv, Ts))
 
 
+# Wall adhesion gamma / psi_L for the contact angles the paper uses (55 deg on
+# the heater, 105, 115 and 125 deg on its nucleate spots, Sections 3.1 and
+# 4.1), found by wetting.calibrate: sessile drops of radius 32 on a 240 x 120
+# fluid, isothermal at T_sat, g = 0, 20 000 FP64 steps.  tests/test_gpu_wetting
+# recomputes the calibration and checks it to 1.5 deg.
+CONTACT_ANGLE_GAMMA = {55.0: -0.7697, 105.0: -0.5376, 115.0: -0.4956, 125.0: -0.4559}
+
+
+def gamma_for_angle(theta, d=None):
+    """Adhesion gamma for a contact angle (degrees) between 55 and 125, by
+    linear interpolation of CONTACT_ANGLE_GAMMA (theta(gamma) is close to
+    linear there)."""
+    d = derived() if d is None else d
+    th = np.array(sorted(CONTACT_ANGLE_GAMMA))
+    if not th[0] <= theta <= th[-1]:
+        raise ValueError(f"contact angle {theta} outside the calibrated range {th[0]}..{th[-1]}")
+    return float(np.interp(theta, th, [CONTACT_ANGLE_GAMMA[t] for t in th])) * d.psi_L
+
+
 @dataclass
 class JobSpec:
     """One boiling-curve job: a domain size, a heater-bottom superheat (units
