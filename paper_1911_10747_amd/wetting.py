@@ -50,13 +50,20 @@ def cap_contact_angle(rho, rho_l, rho_v, wall_y=-0.5, skip_rows=3):
     return math.degrees(math.acos(c)), (xc, yc, r)
 
 
-def sessile_drop(nx, ny, radius, gamma, d=None, precision=pb.PB_FP64, tile=(0, 0)):
+def _params_and_derived(params, d):
+    P = dict(W.BASE_PARAMS if params is None else params)
+    if d is None:
+        d = presets.derived(a=P["a"], b=P["b"], R=P["R"], omega=P["omega"], G=P["G"])
+    return P, d
+
+
+def sessile_drop(nx, ny, radius, gamma, d=None, precision=pb.PB_FP64, tile=(0, 0), params=None):
     """(config, bc kwargs, rho, T) of a drop test: a half disk of liquid of
     the given radius on the middle of the bottom wall (Maxwell densities, tanh
     interface), T = T_sat and isothermal, g = 0; the bottom wall has adhesion
-    gamma, the top wall -psi_V (neutral to vapour)."""
-    d = presets.derived() if d is None else d
-    P = dict(W.BASE_PARAMS)
+    gamma, the top wall -psi_V (neutral to vapour).  params: the physical
+    parameters (default the workload set), d: their derived constants."""
+    P, d = _params_and_derived(params, d)
     P["g"] = 0.0
     cfg = pb.make_config(nx=nx, ny_fluid=ny, ny_solid=1, precision=precision, flags=pb.PB_ISOTHERMAL,
                          tile_x=tile[0], tile_y=tile[1], Tc=d.Tc, rho_L=d.rho_L, rho_V=d.rho_V,
@@ -69,16 +76,16 @@ def sessile_drop(nx, ny, radius, gamma, d=None, precision=pb.PB_FP64, tile=(0, 0
 
 
 def contact_angles(gammas, nx=240, ny=120, radius=32, steps=20000, precision=pb.PB_FP64, d=None,
-                   steps_per_graph=500):
+                   steps_per_graph=500, params=None):
     """Equilibrium contact angle (degrees) for each bottom-wall gamma: one
     drop per gamma, all stepped together in one batched launch.  NaN where a
     drop's run went non-finite (the domain's sticky flag; the others are
     unaffected)."""
-    d = presets.derived() if d is None else d
+    P, d = _params_and_derived(params, d)
     doms = []
     try:
         for g in gammas:
-            cfg, bc, rho, T = sessile_drop(nx, ny, radius, g, d, precision)
+            cfg, bc, rho, T = sessile_drop(nx, ny, radius, g, d, precision, params=P)
             dom = pb.Domain(cfg)
             dom.set_bc(**bc)
             dom.set_fields(rho, T)
@@ -102,7 +109,7 @@ def contact_angles(gammas, nx=240, ny=120, radius=32, steps=20000, precision=pb.
             dom.close()
 
 
-def calibrate(thetas, gamma_range=None, n_coarse=12, n_fine=8, d=None, **kw):
+def calibrate(thetas, gamma_range=None, n_coarse=12, n_fine=8, d=None, params=None, **kw):
     """Bottom-wall gamma giving each wanted contact angle (degrees).  theta
     falls as gamma grows more negative (a more attractive wall), so one
     batched sweep over gamma_range brackets every target; a second sweep over
@@ -111,7 +118,8 @@ def calibrate(thetas, gamma_range=None, n_coarse=12, n_fine=8, d=None, **kw):
     20 to 180 degrees (the drop stays on the wall); at -psi_L the run goes
     non-finite and above about -0.3 psi_L the drop leaves the wall.  Returns
     (gammas, {"coarse": (g, theta), "fine": [(g, theta), ...]})."""
-    d = presets.derived() if d is None else d
+    P, d = _params_and_derived(params, d)
+    kw["params"] = P
     lo, hi = (-0.95 * d.psi_L, -0.3 * d.psi_L) if gamma_range is None else gamma_range
     g0 = np.linspace(lo, hi, n_coarse)
     th0 = contact_angles(g0, d=d, **kw)
@@ -135,3 +143,53 @@ def _bracket(thetas, th):
 
 def _interp(g0, g1, t0, t1, th):
     return g0 if t1 == t0 else g0 + (g1 - g0) * (th - t0) / (t1 - t0)
+
+
+def pressure(rho, T, P):
+    """Pressure the pseudopotential model carries, rho c_s^2 + G psi^2 / 2
+    with c = 1 (Eq. 12), which with psi from Eq. 12-13 is the EOS pressure."""
+    psi = pb.eos_psi(P["a"], P["b"], P["R"], P["omega"], P["Tc"], P["G"], float(rho), float(T))
+    return float(rho) / 3.0 + 0.5 * P["G"] * psi * psi
+
+
+def surface_tension(radii=(12, 16, 20, 24, 28), n=128, steps=20000, precision=pb.PB_FP64, params=None, d=None,
+                    steps_per_graph=500):
+    """Surface tension by Laplace's law in 2-D, dp = sigma / R: static liquid
+    drops of several radii in a periodic n x n box, isothermal at T_sat, g = 0,
+    all in one batched launch.  dp = P(rho at the centre) - P(rho at the
+    corner); R is the equimolar radius, from the liquid excess over the vapour
+    (pi R^2 = sum(rho - rho_out) / (rho_in - rho_out)).  Returns
+    (sigma, intercept, [(R, dp), ...]) of the least-squares line dp(1/R)."""
+    P, d = _params_and_derived(params, d)
+    P.update(g=0.0, Tc=d.Tc)
+    cfg_kw = {k: v for k, v in P.items()}
+    doms, out = [], []
+    try:
+        for r in radii:
+            cfg = pb.make_config(nx=n, ny_fluid=n, ny_solid=0, precision=precision,
+                                 flags=pb.PB_PERIODIC_Y | pb.PB_ISOTHERMAL, rho_L=d.rho_L, rho_V=d.rho_V,
+                                 rho_S=W.RHO_S_OVER_RHO_L * d.rho_L, **cfg_kw)
+            dom = pb.Domain(cfg)
+            dom.set_bc(d.Tsat)
+            dom.set_fields(W.drop_rho(n, n, r, d.rho_L, d.rho_V, width=3.0), np.full((n, n), d.Tsat))
+            doms.append(dom)
+        batch = pb.Batch(doms, steps_per_graph=steps_per_graph)
+        try:
+            batch.step(steps)
+        finally:
+            batch.close()
+        for dom in doms:
+            dom.sync()
+            rho = dom.read(with_f=False)["rho"]
+            c = n // 2
+            r_in = float(rho[c - 1:c + 1, c - 1:c + 1].mean())
+            r_out = float(rho[0, 0])
+            R = math.sqrt(float(np.sum(rho - r_out)) / (r_in - r_out) / math.pi)
+            out.append((R, pressure(r_in, d.Tsat, P) - pressure(r_out, d.Tsat, P)))
+    finally:
+        for dom in doms:
+            dom.close()
+    x = np.array([1.0 / R for R, _ in out])
+    y = np.array([dp for _, dp in out])
+    sigma, icpt = np.polyfit(x, y, 1)
+    return float(sigma), float(icpt), out
