@@ -45,10 +45,11 @@ def algorithmic_bytes(nx, nyf, nys, precision):
 TRAFFIC_FILES = {"roofline": "pmc_traffic_step_4096x2048_fp32dev.txt"}
 
 
-def load_traffic(workload):
-    """HBM bytes per step (both launches) measured with rocprofv3 FETCH_SIZE /
-    WRITE_SIZE and scaled by a copy-kernel calibration, if the measurement was
-    taken on the current kernel source (hash match); else None."""
+def load_profile(workload):
+    """Per-step HBM bytes (both launches) and per-kernel bytes and wavefront
+    VALU instructions, measured with rocprofv3 (FETCH_SIZE / WRITE_SIZE scaled
+    by a copy-kernel calibration, SQ_INSTS_VALU), if the measurement was taken
+    on the current kernel source (hash match); else None."""
     import hashlib
     if workload not in TRAFFIC_FILES:
         return None
@@ -60,7 +61,49 @@ def load_traffic(workload):
     src = open(os.path.join(ROOT, "paper_1911_10747_amd", "csrc", "pb_kernels.hip"), "rb").read()
     if rec.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
         return None
-    return rec.get("roofline_bytes_per_step")
+    return rec
+
+
+def kernel_record(rec, prefix):
+    """The profile entry of the kernel whose name starts with prefix."""
+    if rec is None:
+        return None
+    for k, v in rec.items():
+        if k.startswith(prefix) and isinstance(v, dict):
+            return v
+    return None
+
+
+# FP64 VALU issue: 256 CUs x 4 SIMDs, one wavefront-64 FP64 instruction per
+# SIMD every 4 cycles (16 lanes), 2.4 GHz -> 614.4 G wavefront instructions/s
+# (78.6 TFLOP/s of FP64 FMA).
+VALU_PEAK_GINST = 256 * 4 / 4 * 2.4
+
+
+def per_kernel(nx, nyf, nys, prec, prof, rec):
+    """Each launch against the roof that bounds it: k_flow against HBM
+    (algorithmic bytes: populations in + out and the T read per fluid node;
+    measured bytes from the counters), k_thermal_sweep against FP64 VALU issue
+    (measured wavefront VALU instructions per launch) with its HBM figures
+    beside."""
+    flow_alg = ((144 if prec == 0 else 72) + 8) * nx * nyf
+    th_alg = 16 * nx * (nyf + nys)
+    out = {}
+    for name, ms, alg, bound in (("k_flow", prof["flow_ms"], flow_alg, "hbm"),
+                                 ("k_thermal_sweep", prof["thermal_ms"], th_alg, "alu")):
+        k = {"bound": bound, "ms": round(ms, 5), "algorithmic_bytes": alg,
+             "achieved_gbs": round(alg / (ms * 1e-3) / 1e9, 1),
+             "frac_hbm": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        kr = kernel_record(rec, name)
+        if kr is not None:
+            k["traffic"] = kr["total_bytes"]
+            k["traffic_gbs"] = round(kr["total_bytes"] / (ms * 1e-3) / 1e9, 1)
+            if kr.get("valu_insts"):
+                k["valu_ginst_s"] = round(kr["valu_insts"] / (ms * 1e-3) / 1e9, 1)
+                k["valu_peak_ginst_s"] = VALU_PEAK_GINST
+                k["frac_valu"] = round(kr["valu_insts"] / (ms * 1e-3) / 1e9 / VALU_PEAK_GINST, 4)
+        out[name] = k
+    return out
 
 
 def cpu_baseline(nx, nyf, nys, steps):
@@ -203,7 +246,9 @@ def main():
     alg = algorithmic_bytes(nx, nyf, nys, prec)
     kern_ms = prof["flow_ms"] + prof["thermal_ms"]
     achieved = alg / (kern_ms * 1e-3) / 1e9
-    traffic = load_traffic(args.workload)
+    rec = load_profile(args.workload)
+    traffic = rec.get("roofline_bytes_per_step") if rec else None
+    kernels = per_kernel(nx, nyf, nys, prec, prof, rec)
     out = {
         "metric": "MLUPS (fused pool-boiling step, fluid-node updates per second) and fraction of HBM peak",
         "value": round(mlups, 1),
@@ -230,9 +275,12 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            "traffic_gbs": round(traffic / (kern_ms * 1e-3) / 1e9, 1) if traffic else None,
+            "traffic_frac": round(traffic / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
             "algorithmic_bytes_per_step": alg,
             "flow_ms": round(prof["flow_ms"], 5),
             "thermal_ms": round(prof["thermal_ms"], 5),
+            "kernels": kernels,
         },
     }
     dom.close()
