@@ -170,6 +170,8 @@ def serving_legs(log):
     dq = np.abs(np.array(q32) - np.array(q64)) / np.maximum(np.abs(np.array(q64)), 1e-30)
     out["boiling_curve"] = dict(fp32_batched=b32, fp64_one_at_a_time=b64,
                                 speedup_jobs_per_hour=round(b32["jobs_per_hour"] / b64["jobs_per_hour"], 2),
+                                mean_job_fluid_node_updates=float(np.mean([j["nx"] * j["nyf"] * j["steps"]
+                                                                           for j in curve])),
                                 heat_flux_rel_diff_median=float(np.median(dq)), heat_flux_rel_diff_max=float(dq.max()),
                                 within_3pct=int((dq <= 0.03).sum()))
     stream = W.job_stream(seed=0, n=48, rate_per_s=4.0)
@@ -289,6 +291,11 @@ def main():
     if not args.no_cpu_baseline:
         print(f"bench: oracle on {args.cpu_steps} steps", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(nx, nyf, nys, args.cpu_steps)
+        if "serving" in out:
+            # the same boiling-curve jobs on the oracle, one job per host core
+            bc = out["serving"]["boiling_curve"]
+            bc["cpu_oracle_jobs_per_hour_per_core"] = round(
+                out["cpu_baseline"]["value"] * 1e6 * 3600.0 / bc["mean_job_fluid_node_updates"], 3)
     print(json.dumps(out), flush=True)
 
 
