@@ -1,7 +1,9 @@
 // HIP kernels (gfx950) for one time step of the hybrid pseudopotential
 // phase-change LBM with conjugate heat transfer (arXiv:1911.10747, Section 2).
 //
-// Two launches per step, both bandwidth-bound stencils (no MFMA):
+// Two launches per step, both stencils with no dense contraction (no MFMA); the
+// flow launch is bound by HBM traffic, the energy-equation launch by FP64 VALU
+// issue:
 //   k_flow     pull streaming (Eq. 8, halfway bounce-back, periodic x), the
 //              macroscopic update (Eq. 10), psi from the Peng-Robinson EOS
 //              (Eqs. 12-13) staged with a one-node halo in LDS, the forces
@@ -178,18 +180,6 @@ struct GlobalStore {
 };
 
 
-// Lane exchange with DPP wave shifts (a VALU move, no LDS round trip): wave_shr:1
-// gives lane i the value of lane i-1 (column x-1), wave_shl:1 that of lane i+1.
-// The end lanes receive 0; they are halo columns whose results are discarded.
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v) {
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
-}
-__device__ __forceinline__ double from_left(double v) { return dpp_move<0x138>(v); }   // value at x-1
-__device__ __forceinline__ double from_right(double v) { return dpp_move<0x130>(v); }  // value at x+1
 
 // ------------------------------------------------------------ node update
 // Moments of the pulled populations: rho and j (Eq. 10 without the force)
@@ -488,6 +478,18 @@ struct Coef9 {
     double k0, k1, k2, k3, k4, k5, k6, k7, k8, beta;
 };
 
+// Lane exchange with DPP wave shifts (a VALU move, no LDS round trip): wave_shr:1
+// gives lane i the value of lane i-1 (column x-1), wave_shl:1 that of lane i+1.
+// The end lanes receive 0; they are halo columns whose results are discarded.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double from_left(double v) { return dpp_move<0x138>(v); }   // value at x-1
+__device__ __forceinline__ double from_right(double v) { return dpp_move<0x130>(v); }  // value at x+1
 
 // Harmonic-mean link conductance 2ab/(a+b) in two halves around a shared
 // reciprocal: the divisor to invert (1 where none is needed) and the link
