@@ -68,6 +68,7 @@ class JobSpec:
     spots_per_columns: int = 64      # one +2% hot spot per this many columns (at least one)
     liquid_fraction: float = 0.4     # liquid below this fraction of the fluid height
     gamma_frac: float = 0.7          # heater-wall adhesion gamma = -gamma_frac * psi_L (top wall: -psi_V)
+    contact_angle: float = None      # if set (55..125 deg), the heater-wall gamma from CONTACT_ANGLE_GAMMA
     tile: tuple = (0, 0)
     thermal_tile: int = 0
     flux_every: int = 10
@@ -90,7 +91,8 @@ def initial_state(spec, d=None):
     Tb = d.Tsat + spec.superheat * d.Tc
     n_spots = max(1, spec.nx // spec.spots_per_columns)
     Tb_row = W.spot_Tb(spec.nx, Tb, n_spots, spec.seed)
-    gam = np.full(spec.nx, -spec.gamma_frac * d.psi_L)
+    g_wall = -spec.gamma_frac * d.psi_L if spec.contact_angle is None else gamma_for_angle(spec.contact_angle, d)
+    gam = np.full(spec.nx, g_wall)
     bc = dict(T_top=d.Tsat, Tb=Tb_row, gamma_bot=gam, gamma_top=np.full(spec.nx, -d.psi_V))
     rho = W.layered_rho(spec.nx, spec.nyf, int(round(spec.liquid_fraction * spec.nyf)), d.rho_L, d.rho_V)
     T = W.thermal_init(spec.nx, spec.nys, spec.nyf, d.Tsat, Tb_row)

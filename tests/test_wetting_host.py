@@ -30,3 +30,15 @@ def test_no_cap_raises():
     from paper_1911_10747_amd import wetting
     with pytest.raises(ValueError):
         wetting.cap_contact_angle(np.full((40, 60), 0.38), 6.5, 0.38)
+
+
+def test_jobspec_contact_angle_sets_the_calibrated_gamma():
+    from paper_1911_10747_amd import presets
+    d = presets.derived()
+    spec = presets.JobSpec(nx=32, nyf=20, nys=3, superheat=0.1, contact_angle=55.0)
+    bc, rho, T = presets.initial_state(spec, d)
+    assert np.all(bc["gamma_bot"] == presets.CONTACT_ANGLE_GAMMA[55.0] * d.psi_L)
+    spec = presets.JobSpec(nx=32, nyf=20, nys=3, superheat=0.1)
+    assert np.all(presets.initial_state(spec, d)[0]["gamma_bot"] == -0.7 * d.psi_L)
+    with pytest.raises(ValueError):
+        presets.gamma_for_angle(40.0, d)
