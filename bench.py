@@ -2,8 +2,9 @@
 """Benchmark of the pool-boiling LBM step on one MI355X.
 
 Default workload: the roofline case, a 4096x2048 fluid domain over a 4096x64
-heater, FP32-deviation population storage with FP64 arithmetic (EOS, T, rho),
-one +2% hot spot per 64 heater columns (seed 0), heater-bottom superheat
+heater, FP32-deviation population storage; the flow step computes in FP64,
+the energy equation in FP32 increments over FP64 T (with FP64 EOS derivative
+and stage-1 differences); one +2% hot spot per 64 heater columns (seed 0), heater-bottom superheat
 0.1 Tc, heat flux sampled every 10 steps.  A step is one full time step of the
 method (flow launch + thermal launch [+ flux sample]).  Inputs are resident in
 HBM when the timed region starts.
@@ -26,7 +27,8 @@ HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     # name: (nx, nyf, nys, precision, description)
     "roofline": (4096, 2048, 64, 1, "pool boiling 4096x2048 fluid + 4096x64 heater, FP32-deviation populations, "
-                                    "FP64 EOS/T/rho, 1 hot spot per 64 columns, superheat 0.1 Tc"),
+                                    "FP64 flow/EOS/T/rho, FP32 energy-equation increments, 1 hot spot per 64 "
+                                    "columns, superheat 0.1 Tc"),
     "roofline_fp64": (4096, 2048, 64, 0, "pool boiling 4096x2048 fluid + 4096x64 heater, FP64 populations, "
                                          "1 hot spot per 64 columns, superheat 0.1 Tc"),
     "paper": (400, 400, 20, 1, "pool boiling 400x400 fluid + 400x20 heater, FP32-deviation populations, "
@@ -262,10 +264,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64+f32" if prec else "f64",
         "data": "synthetic (seeded pool-boiling start: Maxwell liquid layer, +2% heater hot spots)",
         "config": {"workload": desc, "nx": nx, "ny_fluid": nyf, "ny_solid": nys,
-                   "storage": "fp32-deviation" if prec else "fp64", "arithmetic": "fp64",
+                   "storage": "fp32-deviation" if prec else "fp64",
+                   "arithmetic": "fp64 flow; fp32 energy-equation increments on fp64 T" if prec else "fp64",
                    "tile": [tx, ty], "thermal_tile": thermal_tile, "autotuned": tuned is not None,
                    "parallelism": "single GPU"},
         "roofline": {

@@ -67,7 +67,7 @@ int max_tiles(int nx, int ny, bool flow) {
 
 // Arena layout of one domain (offsets in bytes from the base).
 struct Layout {
-    size_t desc, dptr, f[2], rho[2], vx, vy, T[2], Tb, Tba, gb, gt, err, flux, tflow, tth, total;
+    size_t desc, dptr, f[2], rho[2], vx, vy, T[2], Tb, Tba, gb, gt, err, flux, sink, tflow, tth, total;
 };
 
 Layout layout_of(const pb_config &c) {
@@ -93,6 +93,7 @@ Layout layout_of(const pb_config &c) {
     L.gt = take((size_t)c.nx * 8);
     L.err = take(sizeof(int32_t));
     L.flux = take(8 * sizeof(double));
+    L.sink = take(64 * sizeof(double));
     L.tflow = take((size_t)max_tiles(c.nx, c.ny_fluid, true) * sizeof(PbTile));
     L.tth = take((size_t)max_tiles(c.nx, c.ny_fluid + c.ny_solid, false) * sizeof(PbTile));
     L.total = o;
@@ -325,6 +326,7 @@ int pb_create_domain(const pb_config *cfg, void *stream, void *dev_mem, size_t d
     h.gtop = (const double *)(d->base + L.gt);
     h.err = (int32_t *)(d->base + L.err);
     h.flux = (double *)(d->base + L.flux);
+    h.sink = (double *)(d->base + L.sink);
     h.fl_every = 1;
     h.a = cfg->a;
     h.b = cfg->b;

@@ -29,6 +29,7 @@ struct PbDesc {
     double T_top;
     // diagnostics
     int32_t *err;        // sticky non-finite flag
+    double *sink;        // [64]: where the energy sweep's halo lanes send their discarded stores
     double *flux;        // [8]: q_bot, q_top, Tw (inst), their sums, count
     // read-back staging (FP64, [9][nyf][pitch] + 3 x [nyf][pitch])
     double *rd_f, *rd_rho, *rd_vx, *rd_vy;

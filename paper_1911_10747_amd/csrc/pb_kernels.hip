@@ -240,7 +240,14 @@ __device__ __forceinline__ bool node_update(cdesc &d, const double f[9], const M
     const double Fax = -psi * sax, Fay = -psi * say;
     const double Fx = Fmx + Fax;
     const double Fy = Fmy + Fay - (rho - d.rho_bar) * d.g;       // Eq. 15
-    const double inv_rho = frcp(rho);
+    // 1/rho, 1/psi^2 and s_nu = 1/tau(rho) (Eq. 5) from one reciprocal of
+    // their product (batch inversion)
+    const double psi2 = psi * psi, tau = d.tau_V + (rho - d.rho_V) * d.ktau;
+    const double pr = rho * psi2;
+    double rr = frcp(pr * tau);
+    const double snu = rr * pr;
+    rr = rr * tau;
+    const double inv_rho = rr * psi2, inv_psi2 = rr * rho;
     double vx = (jx + 0.5 * Fx) * inv_rho;                         // Eq. 10
     double vy = (jy + 0.5 * Fy) * inv_rho;
     if (frozen) { vx = 0.0; vy = 0.0; }
@@ -264,10 +271,9 @@ __device__ __forceinline__ bool node_update(cdesc &d, const double f[9], const M
         const double Fwx = (d.flags & F_FMONLY) ? Fmx : Fmx + Fax;
         const double Fwy = (d.flags & F_FMONLY) ? Fmy : Fmy + Fay;
         const double uF = vx * Fx + vy * Fy;
-        const double cw = 12.0 * d.varpi * d.s_e * (Fwx * Fwx + Fwy * Fwy) * frcp(psi * psi);
+        const double cw = 12.0 * d.varpi * d.s_e * (Fwx * Fwx + Fwy * Fwy) * inv_psi2;
         const double cw2 = (d.flags & F_S2PLUS) ? cw : -cw;
         const double se = d.s_e, sq = d.s_q;
-        const double snu = frcp(d.tau_V + (rho - d.rho_V) * d.ktau);   // Eq. 5
         const double ms1 = m1 - se * (m1 - meq1) + (1.0 - 0.5 * se) * (6.0 * uF) + cw;
         const double ms2 = m2 - se * (m2 - meq2) + (1.0 - 0.5 * se) * (-6.0 * uF) + cw2;
         const double ms3 = jx + Fx;                       // s_j drops out (Eq. 7 + Eq. 10)
@@ -490,24 +496,30 @@ __device__ __forceinline__ double dpp_move(double v) {
 }
 __device__ __forceinline__ double from_left(double v) { return dpp_move<0x138>(v); }   // value at x-1
 __device__ __forceinline__ double from_right(double v) { return dpp_move<0x130>(v); }  // value at x+1
+__device__ __forceinline__ float from_left(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float from_right(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xF, 0xF, true));
+}
 
 // Harmonic-mean link conductance 2ab/(a+b) in two halves around a shared
 // reciprocal: the divisor to invert (1 where none is needed) and the link
 // from the inverted sum.  A negative value marks the T_top row, whose links
 // take the conductance of the other node; a zero sum gives a zero link.  FL:
 // both conductances are fluid ones, positive in any physical state.
-template <bool FL>
-__device__ __forceinline__ double hlink_div(double a, double b, double s) {
+template <bool FL, typename R>
+__device__ __forceinline__ R hlink_div(R a, R b, R s) {
     if constexpr (FL) return s;
-    return (a < 0.0 || b < 0.0 || !(s > 0.0)) ? 1.0 : s;
+    return (a < R(0) || b < R(0) || !(s > R(0))) ? R(1) : s;
 }
-template <bool FL>
-__device__ __forceinline__ double hlink_sel(double a, double b, double s, double inv_s) {
-    const double h = 2.0 * a * b * inv_s;
+template <bool FL, typename R>
+__device__ __forceinline__ R hlink_sel(R a, R b, R s, R inv_s) {
+    const R h = R(2) * a * b * inv_s;
     if constexpr (FL) return h;
-    if (a < 0.0) return b;
-    if (b < 0.0) return a;
-    return s > 0.0 ? h : 0.0;
+    if (a < R(0)) return b;
+    if (b < R(0)) return a;
+    return s > R(0) ? h : R(0);
 }
 
 struct RowIn {
@@ -731,6 +743,274 @@ __device__ __forceinline__ void thermal_strip(cdesc &d, const PbTile &te, int k,
     if (bad) flag_error(d);
 }
 
+// ------------------------------------------- energy step, FP32 arithmetic
+// The same sweep for FP32-deviation storage with the energy equation's
+// arithmetic in FP32 (the FP32 VALU issues twice as many instructions per
+// cycle as the FP64 one).  What stays FP64: T in HBM, the density and the
+// EOS-derivative coefficients A(rho), B(rho) of the latent term, the
+// differences T(x + e_i) - T(x) that enter stage 1, and the final update
+// T(t+1) = T(t) + (h1 + 2 h2 + 2 h3 + h4) / 6, whose FP32 increment is added to
+// the FP64 T.  The stages are carried as increments: with the operator
+// K(T) = L T + beta sqrt(T) (L linear, L T = sum_i k_i T(x + e_i)),
+//   h1 = L T + beta sqrt(T),
+//   h_k = L T + c_k L h_(k-1) + beta sqrt(T + c_k h_(k-1)),  c = 1/2, 1/2, 1,
+// and L T = sum_(i>0) k_i (T(x + e_i) - T(x)) + (sum_i k_i) T(x), where the
+// diffusion and advection weights sum to zero and sum_i k_i is the linear part
+// of the latent term.  Every rounding error is then relative to an increment
+// or a local difference, never to T itself, so a steady field (the heater)
+// gets no spurious source.
+struct Coef9s {
+    float k0, k1, k2, k3, k4, k5, k6, k7, k8, beta;
+};
+
+// A row as loaded: raw values only, so that nothing waits on the loads
+// before the row is used two iterations later.  lam is set for the rows that
+// need no load (heater, T_top); a fluid row's comes from rho when used.
+struct RowInS {
+    int kind;
+    double T0, rho;
+    float lam, vx, vy;
+};
+
+template <bool FL>
+__device__ __forceinline__ RowInS load_row_s(cdesc &d, const double PB_GAS *Tin, const double PB_GAS *rho,
+                                             const float PB_GAS *vxg, const float PB_GAS *vyg, int n, int xg,
+                                             bool pery, float cvchi, float lam_s) {
+    RowInS r{KIND_NONE, 0.0, 0.0, 0.0f, 0.0f, 0.0f};
+    if constexpr (FL) {
+        const uint32_t fi = (uint32_t)(n - d.nys) * (uint32_t)d.pitch + (uint32_t)xg;
+        r.T0 = Tin[(uint32_t)n * (uint32_t)d.pitch + (uint32_t)xg];
+        r.rho = rho[fi];
+        r.vx = vxg[fi];
+        r.vy = vyg[fi];
+        r.kind = KIND_FLUID;
+        return r;
+    }
+    int rr = n;
+    if (pery) {
+        rr %= d.nr;
+        if (rr < 0) rr += d.nr;
+    }
+    if (rr >= 0 && rr < d.nr) {
+        r.T0 = Tin[(uint32_t)rr * (uint32_t)d.pitch + (uint32_t)xg];
+        if (rr < d.nys) {
+            r.lam = lam_s;
+            r.kind = (rr == 0 && !pery) ? KIND_FIXED : KIND_SOLID;
+        } else {
+            const uint32_t fi = (uint32_t)(rr - d.nys) * (uint32_t)d.pitch + (uint32_t)xg;
+            r.rho = rho[fi];
+            r.vx = vxg[fi];
+            r.vy = vyg[fi];
+            r.kind = KIND_FLUID;
+        }
+    } else if (!pery && rr == d.nr) {
+        r.T0 = d.T_top;
+        r.lam = -1.0f;
+        r.kind = KIND_FIXED;
+    }
+    return r;
+}
+
+__device__ __forceinline__ float frcp_s(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return __builtin_fmaf(__builtin_fmaf(-x, r, 1.0f), r, r);
+}
+
+// L applied to nine values (centre row S*, row above N*, row below *_)
+__device__ __forceinline__ float lin9s(const Coef9s &c, float Sc, float SR, float SL, float Nc, float NR, float NL,
+                                       float Sc_, float SR_, float SL_) {
+    const float rm = c.k0 * Sc + c.k1 * SR + c.k3 * SL;
+    const float ra = c.k2 * Nc + c.k5 * NR + c.k6 * NL;
+    const float rb = c.k4 * Sc_ + c.k7 * SL_ + c.k8 * SR_;
+    return rm + (ra + rb);
+}
+
+// stage k >= 2: h_k = L T + c L h_(k-1) + beta sqrt(T + c h_(k-1)); sqrt is
+// the hardware square root (about 1 ulp)
+template <bool FL>
+__device__ __forceinline__ float stage_s(const Coef9s &c, int kind, float LT, float ck, float Tf, float Sc, float SR,
+                                         float SL, float Nc, float NR, float NL, float Sc_, float SR_, float SL_) {
+    float K = LT + ck * lin9s(c, Sc, SR, SL, Nc, NR, NL, Sc_, SR_, SL_);
+    if (FL || kind == KIND_FLUID) K += c.beta * __builtin_amdgcn_sqrtf(Tf + ck * Sc);
+    return K;
+}
+
+template <int H, int UNR, bool FL>
+__device__ __forceinline__ void thermal_strip_sp(cdesc &d, const PbTile &te, int k, int lane) {
+    const bool pery = !FL && (d.flags & F_PERY) != 0;
+    const int pin = (int)((d.par0 + k) & 1), pout = pin ^ 1;
+    const int64_t t1 = d.t0 + k + 1;
+    const double PB_GAS *Tin = gcast<double>(d.T[pin]);
+    double PB_GAS *Tout = gcast_w<double>(d.T[pout]);
+    const double PB_GAS *rhog = gcast<double>(d.rho[pout]);   // rho(t) written by this step's flow
+    const float PB_GAS *vxg = gcast<float>(d.vx);
+    const float PB_GAS *vyg = gcast<float>(d.vy);
+    int xg = (te.x0 - 4 + lane) % d.nx;
+    if (xg < 0) xg += d.nx;
+    const bool out_lane = lane >= 4 && lane < 60 && (te.x0 + lane - 4) < d.nx;
+    double PB_GAS *Tst = out_lane ? Tout : gcast_w<double>(d.sink);
+    const float cvchi = (float)d.Cvchi, lam_s = (float)d.lambda_S, cv = (float)d.Cv;
+    const float c1_solid = (float)(1.0 / (d.rho_S * d.C_S));
+    const float lat_a = (float)(d.kappa / d.Tc), lat_b = (float)((1.0 + d.kappa) * d.inv_sqrtTc);
+    const float W1 = 6.0f / 9.0f, W2 = 6.0f / 36.0f, A1 = 3.0f / 9.0f, A2 = 3.0f / 36.0f;
+
+    // carried state; "_1" = row n-1, "_2" = row n-2 and so on
+    int kind_1 = KIND_NONE;
+    float lam_1 = 0.0f, lamR_1 = 0.0f;
+    double rho_1 = 0.0;
+    float vx_1 = 0.0f, vy_1 = 0.0f, vy_2 = 0.0f;
+    float p_1 = 0.0f, m_1 = 0.0f, p_2 = 0.0f, m_2 = 0.0f;
+    float lN_2 = 0.0f, lNEL_2 = 0.0f, lNWR_2 = 0.0f;
+    double T0_1 = 0.0, T0_2 = 0.0, T0_3 = 0.0, T0_4 = 0.0;
+    // FP64 differences rounded to FP32: T(x+1) - T(x) and T(x-1) - T(x) of a
+    // row, and T(row n-1) - T(row n-2)
+    float dR_1 = 0.0f, dL_1 = 0.0f, dR_2 = 0.0f, dL_2 = 0.0f, dV_1 = 0.0f;
+    float LT_2 = 0.0f, LT_3 = 0.0f, LT_4 = 0.0f;              // L T(t) of the row
+    float h1_2 = 0.0f, h1L_2 = 0.0f, h1R_2 = 0.0f, h1_3 = 0.0f, h1L_3 = 0.0f, h1R_3 = 0.0f;
+    float h2_3 = 0.0f, h2L_3 = 0.0f, h2R_3 = 0.0f, h2_4 = 0.0f, h2L_4 = 0.0f, h2R_4 = 0.0f;
+    float h3_4 = 0.0f, h3L_4 = 0.0f, h3R_4 = 0.0f, h3_5 = 0.0f, h3L_5 = 0.0f, h3R_5 = 0.0f;
+    float acc_2 = 0.0f, acc_3 = 0.0f, acc_4 = 0.0f;
+    int kd_2 = KIND_NONE, kd_3 = KIND_NONE, kd_4 = KIND_NONE;
+    Coef9s cf_2{}, cf_3{}, cf_4{};
+    bool bad = false;
+
+    const int nbeg = te.y0 - 4, nend = te.y0 + H + 3;
+    RowInS nx1 = load_row_s<FL>(d, Tin, rhog, vxg, vyg, nbeg, xg, pery, cvchi, lam_s);
+    RowInS nx2 = load_row_s<FL>(d, Tin, rhog, vxg, vyg, nbeg + 1, xg, pery, cvchi, lam_s);
+#pragma unroll UNR
+    for (int j = 0; j < H + 8; ++j) {
+        const int n = nbeg + j;
+        RowInS cur = nx1;
+        nx1 = nx2;
+        if (n + 2 <= nend) nx2 = load_row_s<FL>(d, Tin, rhog, vxg, vyg, n + 2, xg, pery, cvchi, lam_s);
+        // keep the loads of row n+2 here: the scheduler would otherwise sink
+        // them next to their use to save registers and lose the prefetch
+        __builtin_amdgcn_sched_barrier(0);
+        if (FL || cur.kind == KIND_FLUID) cur.lam = cvchi * (float)cur.rho;
+
+        const float lamL = from_left(cur.lam), lamR = from_right(cur.lam);
+        const float dR = (float)(from_right(cur.T0) - cur.T0), dL = (float)(from_left(cur.T0) - cur.T0);
+        const float dV = (float)(cur.T0 - T0_1);
+        const float p = cur.vx + cur.vy, m = cur.vx - cur.vy;
+
+        // operator of row a = n-1: the four link sums and rho C_V share one
+        // reciprocal (batch inversion); A(rho), B(rho) in FP64
+        const float sE = lam_1 + lamR_1, sN = lam_1 + cur.lam, sNE = lam_1 + lamR, sNW = lam_1 + lamL;
+        const bool fluid_1 = FL || kind_1 == KIND_FLUID;
+        const float dE = hlink_div<FL>(lam_1, lamR_1, sE), dN = hlink_div<FL>(lam_1, cur.lam, sN);
+        const float dNE = hlink_div<FL>(lam_1, lamR, sNE), dNW = hlink_div<FL>(lam_1, lamL, sNW);
+        const float dC = fluid_1 ? (float)rho_1 * cv : 1.0f;
+        const float p1 = dE * dN, p2 = p1 * dNE, p3 = p2 * dNW, p4 = p3 * dC;
+        float rr = frcp_s(p4);
+        const float iC = rr * p3;
+        rr = rr * dC;
+        const float iNW = rr * p2;
+        rr = rr * dNW;
+        const float iNE = rr * p1;
+        rr = rr * dNE;
+        const float iN = rr * dE, iE = rr * dN;
+        const float lE = hlink_sel<FL>(lam_1, lamR_1, sE, iE), lN = hlink_sel<FL>(lam_1, cur.lam, sN, iN);
+        const float lNE = hlink_sel<FL>(lam_1, lamR, sNE, iNE), lNW = hlink_sel<FL>(lam_1, lamL, sNW, iNW);
+        const float lW = from_left(lE);
+        // Eq. 27 on v, grouped as U(x+1) - V(x-1) + (vy(above) - vy(below)) / 9
+        const float U = (1.0f / 9.0f) * vx_1 + (1.0f / 36.0f) * (p + m_2);
+        const float V = (1.0f / 9.0f) * vx_1 + (1.0f / 36.0f) * (m + p_2);
+        const float UR = from_right(U), VL = from_left(V);
+        Coef9s cf{};
+        float lin = 0.0f;
+        if (FL || kind_1 == KIND_FLUID || kind_1 == KIND_SOLID) {
+            const float C1 = fluid_1 ? iC : c1_solid;
+            const float c1 = W1 * C1 * lE, c2 = W1 * C1 * lN, c3 = W1 * C1 * lW, c4 = W1 * C1 * lN_2;
+            const float c5 = W2 * C1 * lNE, c6 = W2 * C1 * lNW, c7 = W2 * C1 * lNEL_2, c8 = W2 * C1 * lNWR_2;
+            cf.k0 = -(((c1 + c2) + (c3 + c4)) + ((c5 + c6) + (c7 + c8)));
+            cf.k1 = c1; cf.k2 = c2; cf.k3 = c3; cf.k4 = c4;
+            cf.k5 = c5; cf.k6 = c6; cf.k7 = c7; cf.k8 = c8;
+            if (fluid_1) {
+                const double br = d.b * rho_1;
+                const double q1 = 1.0 - br, q2 = 1.0 + 2.0 * br - br * br;
+                const double iq = frcp(q1 * q2);
+                const float A = (float)(rho_1 * d.R * q2 * iq);                     // rho R / (1 - b rho)
+                const float B = (float)(d.a * d.kappa * rho_1 * rho_1 * q1 * iq);   // a kappa rho^2 / (1 + 2 b rho - b^2 rho^2)
+                const float divv = 3.0f * ((UR - VL) + (1.0f / 9.0f) * (cur.vy - vy_2));
+                const float AL = -C1 * divv * A, BE = -C1 * divv * B;
+                lin = AL - BE * lat_a;
+                cf.k0 += lin;
+                cf.beta = BE * lat_b;
+                // advection -v.grad T with Eq. 27
+                cf.k1 -= A1 * vx_1;  cf.k3 += A1 * vx_1;
+                cf.k2 -= A1 * vy_1;  cf.k4 += A1 * vy_1;
+                cf.k5 -= A2 * p_1;  cf.k7 += A2 * p_1;
+                cf.k6 += A2 * m_1;  cf.k8 -= A2 * m_1;
+            }
+        }
+
+        // stage 1 on row n-1 from the differences to T(x) (input T rows n-2,
+        // n-1, n); a diagonal difference is a row difference plus a column one
+        const float Tf_1 = (float)T0_1;
+        const float dS = -dV_1;
+        const float LT = (cf.k1 * dR_1 + cf.k3 * dL_1) + (cf.k2 * dV + cf.k5 * (dV + dR) + cf.k6 * (dV + dL)) +
+                         (cf.k4 * dS + cf.k7 * (dS + dL_2) + cf.k8 * (dS + dR_2)) + lin * Tf_1;
+        float h1 = LT;
+        if (FL || kind_1 == KIND_FLUID) h1 += cf.beta * __builtin_amdgcn_sqrtf(Tf_1);
+        const float acc1 = h1;
+        const float h1L = from_left(h1), h1R = from_right(h1);
+        // stage 2 on row n-2 (input h1 rows n-3, n-2, n-1)
+        const float h2 = stage_s<FL>(cf_2, kd_2, LT_2, 0.5f, (float)T0_2, h1_2, h1R_2, h1L_2, h1, h1R, h1L, h1_3,
+                                     h1R_3, h1L_3);
+        const float acc2 = acc_2 + 2.0f * h2;
+        const float h2L = from_left(h2), h2R = from_right(h2);
+        // stage 3 on row n-3 (input h2 rows n-4, n-3, n-2)
+        const float h3 = stage_s<FL>(cf_3, kd_3, LT_3, 0.5f, (float)T0_3, h2_3, h2R_3, h2L_3, h2, h2R, h2L, h2_4,
+                                     h2R_4, h2L_4);
+        const float acc3 = acc_3 + 2.0f * h3;
+        const float h3L = from_left(h3), h3R = from_right(h3);
+        // stage 4 and the update on row e = n-4 (input h3 rows n-5, n-4, n-3)
+        const float h4 = stage_s<FL>(cf_4, kd_4, LT_4, 1.0f, (float)T0_4, h3_4, h3R_4, h3L_4, h3, h3R, h3L, h3_5,
+                                     h3R_5, h3L_5);
+        const int e = n - 4;
+        if constexpr (FL) {
+            // every row of the strip is in the domain: the halo lanes store to
+            // the sink instead of branching around the store, so the rows form
+            // one straight-line block the compiler can schedule across
+            if (j >= 8) {
+                const double Tn = T0_4 + (double)((1.0f / 6.0f) * (acc_4 + h4));
+                const uint32_t off = out_lane ? (uint32_t)e * (uint32_t)d.pitch + (uint32_t)xg : (uint32_t)lane;
+                Tst[off] = Tn;
+                bad = bad || (out_lane && !(Tn - Tn == 0.0));
+            }
+        } else if (out_lane && e >= te.y0 && e < te.y0 + H && e >= 0 && e < d.nr) {
+            double Tn;
+            if (kd_4 == KIND_FIXED) {
+                Tn = (t1 >= d.alt_t0 && t1 < d.alt_t1) ? gcast<double>(d.Tb_alt)[xg]
+                                                       : gcast<double>(d.Tb)[xg];   // T_b(x, t+1)
+            } else {
+                Tn = T0_4 + (double)((1.0f / 6.0f) * (acc_4 + h4));
+            }
+            Tout[(uint32_t)e * (uint32_t)d.pitch + (uint32_t)xg] = Tn;
+            bad = bad || !(Tn - Tn == 0.0);
+        }
+
+        // shift the windows by one row
+        cf_4 = cf_3; cf_3 = cf_2; cf_2 = cf;
+        LT_4 = LT_3; LT_3 = LT_2; LT_2 = LT;
+        h3_5 = h3_4; h3L_5 = h3L_4; h3R_5 = h3R_4;
+        h3_4 = h3; h3L_4 = h3L; h3R_4 = h3R;
+        h2_4 = h2_3; h2L_4 = h2L_3; h2R_4 = h2R_3;
+        h2_3 = h2; h2L_3 = h2L; h2R_3 = h2R;
+        h1_3 = h1_2; h1L_3 = h1L_2; h1R_3 = h1R_2;
+        h1_2 = h1; h1L_2 = h1L; h1R_2 = h1R;
+        acc_4 = acc3; acc_3 = acc2; acc_2 = acc1;
+        kd_4 = kd_3; kd_3 = kd_2; kd_2 = kind_1;
+        T0_4 = T0_3; T0_3 = T0_2; T0_2 = T0_1; T0_1 = cur.T0;
+        dR_2 = dR_1; dL_2 = dL_1; dR_1 = dR; dL_1 = dL; dV_1 = dV;
+        lN_2 = lN; lNEL_2 = from_left(lNE); lNWR_2 = from_right(lNW);
+        vy_2 = vy_1; p_2 = p_1; m_2 = m_1;
+        vx_1 = cur.vx; vy_1 = cur.vy; p_1 = p; m_1 = m;
+        lam_1 = cur.lam; lamR_1 = lamR; rho_1 = cur.rho; kind_1 = cur.kind;
+    }
+    if (bad) flag_error(d);
+}
+
 template <typename VT, int H, int WPE, int UNR>
 __global__ __launch_bounds__(64, WPE) void k_thermal_sweep(const PbDesc *const *__restrict__ dps,
                                                             const PbTile *__restrict__ tiles, int ntiles, int k) {
@@ -739,8 +1019,13 @@ __global__ __launch_bounds__(64, WPE) void k_thermal_sweep(const PbDesc *const *
         const PbTile te = tiles[tl];
         cdesc &d = *(const PbDesc PB_CAS *)dps[te.dom];
         const bool fl = !(d.flags & F_PERY) && te.y0 - 4 >= d.nys && te.y0 + H + 3 < d.nr;
-        if (fl) thermal_strip<VT, H, UNR, true>(d, te, k, lane);
-        else thermal_strip<VT, H, UNR, false>(d, te, k, lane);
+        if constexpr (std::is_same<VT, float>::value) {
+            if (fl) thermal_strip_sp<H, UNR, true>(d, te, k, lane);
+            else thermal_strip_sp<H, UNR, false>(d, te, k, lane);
+        } else {
+            if (fl) thermal_strip<VT, H, UNR, true>(d, te, k, lane);
+            else thermal_strip<VT, H, UNR, false>(d, te, k, lane);
+        }
     }
 }
 
