@@ -2,7 +2,7 @@
 // phase-change LBM with conjugate heat transfer (arXiv:1911.10747, Section 2).
 //
 // Two launches per step, both stencils with no dense contraction (no MFMA); the
-// flow launch is bound by HBM traffic, the energy-equation launch by FP64 VALU
+// flow launch is bound by HBM traffic, the energy-equation launch by VALU
 // issue:
 //   k_flow     pull streaming (Eq. 8, halfway bounce-back, periodic x), the
 //              macroscopic update (Eq. 10), psi from the Peng-Robinson EOS
@@ -19,8 +19,9 @@
 //
 // Layout: SoA populations f[i][y][x] with x fastest and a padded row pitch; a
 // wavefront covers 64 consecutive x of one row, so every pull and store is a
-// coalesced row segment.  All arithmetic is FP64; PB_FP32_DEV stores
-// f*_i - w_i rho(x) in FP32 and rebuilds f in FP64 on load.
+// coalesced row segment.  The flow step computes in FP64; PB_FP32_DEV stores
+// f*_i - w_i rho(x) in FP32 and rebuilds f in FP64 on load, and runs the
+// energy equation in FP32 increments over FP64 T (see the FP32 sweep below).
 #include <type_traits>
 
 #include "pb_internal.h"
