@@ -96,6 +96,40 @@ def test_frozen_flow_conduction():
     assert g["flux"]["q_bottom_mean"] == pytest.approx(o["flux"]["q_bottom_mean"], rel=1e-11)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_steady_conduction_closed_form(precision):
+    """Steady 1-D conduction through a heater under a thin frozen liquid layer,
+    against the closed form: the same flux crosses every row link, so T is
+    piecewise linear with link resistances 1/lambda_S in the heater, the
+    harmonic mean at the interface and 1/lambda_L in the liquid and on the
+    link to the T_sat row.  A steady field is where rounding T itself in FP32
+    would act as a standing source; the FP32 energy equation works on FP64
+    differences and FP32 increments, so its profile stays on the closed form."""
+    nx, nyf, nys = 64, 4, 24
+    P, d = params(nx, nyf, nys, frozen_flow=1)
+    lamL, lamS = P["Cvchi"] * d["rho_L"], P["lambda_S"]
+    Tb, Tt = d["Tsat"] + 0.1 * d["Tc"], d["Tsat"]
+    g = gpu_domain(P, dict(T_top=Tt, Tb=np.full(nx, Tb)), np.full((nyf, nx), d["rho_L"]),
+                   W.thermal_init(nx, nys, nyf, Tt, np.full(nx, Tb)), precision)
+    n = 80000                     # about 45 e-folding times of the slowest mode
+    g.step(n - 1)
+    g.flux_window(n, n + 1, 1)
+    g.step(1)
+    res = [1 / lamS] * (nys - 1) + [(lamS + lamL) / (2 * lamS * lamL)] + [1 / lamL] * (nyf - 1) + [1 / lamL]
+    q = (Tb - Tt) / sum(res)
+    prof = Tb - q * np.concatenate([[0.0], np.cumsum(res)])[: nys + nyf]
+    T = g.read(with_f=False)["T"]
+    hf = g.heat_flux()
+    g.close()
+    errT = float(np.max(np.abs(T - prof[:, None])) / np.max(prof))
+    errq = abs(hf["q_bottom_inst"] - q) / q
+    print(f"steady conduction precision={precision}: T {errT:.2e}, q_bottom {errq:.2e}, "
+          f"q_top {abs(hf['q_top_inst'] - q) / q:.2e}", flush=True)
+    assert errT <= (1e-12 if precision == 0 else 1e-7)
+    assert errq <= (1e-9 if precision == 0 else 1e-5)
+    assert hf["q_top_inst"] == pytest.approx(q, rel=1e-9 if precision == 0 else 1e-5)
+
+
 @pytest.mark.parametrize("tile", [(0, 0), (32, 16)])
 @pytest.mark.parametrize("shape", [(1, 1, 3), (2, 3, 3), (3, 70, 4), (130, 2, 3), (2, 1, 1), (5, 4, 2)])
 def test_degenerate_shapes(shape, tile):
