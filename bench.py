@@ -148,10 +148,11 @@ def cpu_baseline(nx, nyf, nys, steps):
                        f"{dt:.1f} s")
 
 
-def _serve_jobs(jobs, precision, batching, max_slots, mem_budget, realtime, time_scale=1.0):
+def _serve_jobs(jobs, precision, batching, max_slots, mem_budget, realtime, time_scale=1.0, tiles=None):
     from paper_1911_10747_amd import presets, serve
+    tile, tv = (tiles["tile"], tiles["thermal_tile"]) if tiles else ((0, 0), 0)
     srv = serve.Server(mem_budget=mem_budget, max_slots=max_slots, precision=precision, chunk_steps=2000,
-                       graph_steps=100 if batching else 0, batching=batching)
+                       graph_steps=100 if batching else 0, batching=batching, tile=tile, thermal_tile=tv)
     if realtime:
         res, wall = serve.run_trace(srv, jobs, time_scale=time_scale, max_wall_s=900)
     else:
@@ -173,15 +174,24 @@ def serving_legs(log):
     (heater 1/20 of the height), superheat U[0.02, 0.30] Tc, 20000 steps, all
     submitted at once; (2) a Poisson stream of 48 jobs, sizes 64..2048 x
     64..1024, 5000-20000 steps, arrival rate 4 jobs/s.  FP32-deviation
-    continuous batching against FP64 one job at a time, same jobs."""
+    continuous batching against FP64 one job at a time, same jobs.  Tile shapes
+    for each precision come from the batch autotuner run on the curve's job
+    mix (outside the timed legs)."""
     import numpy as np
     import workloads as W
+    from paper_1911_10747_amd import autotune, presets
     out = {}
     curve = W.batch_jobs(seed=0, n=32, steps=20000)
+    tiles = {}
+    for prec in (1, 0):
+        specs = [presets.JobSpec(nx=j["nx"], nyf=j["nyf"], nys=j["nys"], superheat=j["superheat"], steps=j["steps"],
+                                 seed=j["seed"], precision=prec) for j in curve]
+        tiles[prec] = autotune.tune_batch(specs, log=log)
+        log(f"serving: tiles for precision {prec}: flow {tiles[prec]['tile']}, thermal {tiles[prec]['thermal_tile']}")
     log("serving: boiling curve, 32 jobs, FP32 batched")
-    b32, q32 = _serve_jobs(curve, 1, True, 64, 32 << 30, realtime=False)
+    b32, q32 = _serve_jobs(curve, 1, True, 64, 32 << 30, realtime=False, tiles=tiles[1])
     log("serving: boiling curve, 32 jobs, FP64 one at a time")
-    b64, q64 = _serve_jobs(curve, 0, False, 1, 32 << 30, realtime=False)
+    b64, q64 = _serve_jobs(curve, 0, False, 1, 32 << 30, realtime=False, tiles=tiles[0])
     dq = np.abs(np.array(q32) - np.array(q64)) / np.maximum(np.abs(np.array(q64)), 1e-30)
     out["boiling_curve"] = dict(fp32_batched=b32, fp64_one_at_a_time=b64,
                                 speedup_jobs_per_hour=round(b32["jobs_per_hour"] / b64["jobs_per_hour"], 2),
@@ -191,10 +201,13 @@ def serving_legs(log):
                                 within_3pct=int((dq <= 0.03).sum()))
     stream = W.job_stream(seed=0, n=48, rate_per_s=4.0)
     log("serving: Poisson stream, 48 jobs, FP32 continuous batching")
-    s32, q32 = _serve_jobs(stream, 1, True, 32, 4 << 30, realtime=True)
+    s32, q32 = _serve_jobs(stream, 1, True, 32, 4 << 30, realtime=True, tiles=tiles[1])
     log("serving: Poisson stream, 48 jobs, FP64 one at a time")
-    s64, q64 = _serve_jobs(stream, 0, False, 1, 4 << 30, realtime=True)
+    s64, q64 = _serve_jobs(stream, 0, False, 1, 4 << 30, realtime=True, tiles=tiles[0])
     dq = np.abs(np.array(q32) - np.array(q64)) / np.maximum(np.abs(np.array(q64)), 1e-30)
+    out["tiles"] = {("fp32_deviation" if p else "fp64"): dict(flow=list(t["tile"]), thermal=t["thermal_tile"],
+                                                            ms_per_step_curve_mix=round(t["ms_per_step"], 4))
+                    for p, t in tiles.items()}
     out["poisson_stream"] = dict(rate_jobs_per_s=4.0, fp32_batched=s32, fp64_one_at_a_time=s64,
                                  heat_flux_rel_diff_median=float(np.median(dq)),
                                  heat_flux_rel_diff_max=float(dq.max()), within_3pct=int((dq <= 0.03).sum()))

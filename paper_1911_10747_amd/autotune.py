@@ -7,6 +7,7 @@ launch (pb_profile_steps).  Results are cached per (nx, ny_fluid, ny_solid,
 precision) in a JSON file.  Tiling never changes results: per-node arithmetic
 is the same for every variant (checked bit for bit by the GPU tests).
 """
+import dataclasses
 import json
 import os
 
@@ -73,3 +74,53 @@ def tune(nx, nyf, nys, precision=pb.PB_FP32_DEV, steps=30, warmup=5, use_cache=T
         cache[key] = dict(r, tile=list(best_tile))
         save_cache(cache)
     return r
+
+
+def _time_batch(specs, steps, warmup, steps_per_graph):
+    import time
+    doms = [presets.make_domain(s, with_window=False) for s in specs]
+    try:
+        b = pb.Batch(doms, steps_per_graph=steps_per_graph)
+        try:
+            b.step(warmup)
+            for dm in doms:
+                dm.sync()
+            t0 = time.perf_counter()
+            b.step(steps)
+            for dm in doms:
+                dm.sync()
+            return (time.perf_counter() - t0) / steps * 1e3
+        finally:
+            b.close()
+    finally:
+        for dm in doms:
+            dm.close()
+
+
+def tune_batch(specs, steps=300, warmup=50, steps_per_graph=100, log=None):
+    """Tile shapes for a batch of domains stepped together (a job mix): every
+    flow tile shape timed with the default thermal variant, then every thermal
+    variant with the best flow tile, each as the wall time per step of the
+    whole batch (graph replay, as the server runs it).  Small and ragged
+    domains favour other shapes than one large domain.  Returns
+    dict(tile=(bx, by), thermal_tile=v, ms_per_step=..., all=...)."""
+    specs = list(specs)
+
+    def with_tiles(tile, tv):
+        return [dataclasses.replace(s, tile=tile, thermal_tile=tv) for s in specs]
+
+    flow = {}
+    for tile in FLOW_TILES:
+        flow[tile] = _time_batch(with_tiles(tile, 0), steps, warmup, steps_per_graph)
+        if log:
+            log(f"autotune batch of {len(specs)}: flow tile {tile}: {flow[tile]:.4f} ms/step")
+    best_tile = min(flow, key=flow.get)
+    therm = {0: flow[best_tile]}
+    for v in THERMAL_VARIANTS[1:]:
+        therm[v] = _time_batch(with_tiles(best_tile, v), steps, warmup, steps_per_graph)
+        if log:
+            log(f"autotune batch of {len(specs)}: thermal variant {v}: {therm[v]:.4f} ms/step")
+    best_v = min(therm, key=therm.get)
+    return dict(tile=best_tile, thermal_tile=best_v, ms_per_step=therm[best_v],
+                all={f"{a}x{b}/0": t for (a, b), t in flow.items()} | {f"{best_tile[0]}x{best_tile[1]}/{v}": t
+                                                                        for v, t in therm.items()})

@@ -72,3 +72,16 @@ def test_fp32_server_heat_flux_matches_fp64():
     q64, q32 = np.array(out[0]), np.array(out[1])
     print("q64", q64, "q32", q32, flush=True)
     np.testing.assert_allclose(q32, q64, rtol=1e-4)
+
+
+def test_batch_autotuner_picks_a_listed_shape():
+    """The batch autotuner times every flow tile and thermal variant on the
+    whole mix and returns one of them (tiling never changes results, which the
+    bit-identity tests check)."""
+    from paper_1911_10747_amd import autotune, presets
+    specs = [presets.JobSpec(nx=nx, nyf=ny, nys=4, superheat=0.1, steps=100, seed=i)
+             for i, (nx, ny) in enumerate([(96, 64), (150, 80), (64, 40)])]
+    r = autotune.tune_batch(specs, steps=20, warmup=5, steps_per_graph=10)
+    assert r["tile"] in autotune.FLOW_TILES
+    assert r["thermal_tile"] in autotune.THERMAL_VARIANTS
+    assert r["ms_per_step"] > 0 and len(r["all"]) == len(autotune.FLOW_TILES) + len(autotune.THERMAL_VARIANTS) - 1
