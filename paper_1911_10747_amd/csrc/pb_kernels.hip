@@ -776,7 +776,7 @@ struct RowInS {
 template <bool FL>
 __device__ __forceinline__ RowInS load_row_s(cdesc &d, const double PB_GAS *Tin, const double PB_GAS *rho,
                                              const float PB_GAS *vxg, const float PB_GAS *vyg, int n, int xg,
-                                             bool pery, float cvchi, float lam_s) {
+                                             bool pery, float lam_s) {
     RowInS r{KIND_NONE, 0.0, 0.0, 0.0f, 0.0f, 0.0f};
     if constexpr (FL) {
         const uint32_t fi = (uint32_t)(n - d.nys) * (uint32_t)d.pitch + (uint32_t)xg;
@@ -876,14 +876,14 @@ __device__ __forceinline__ void thermal_strip_sp(cdesc &d, const PbTile &te, int
     bool bad = false;
 
     const int nbeg = te.y0 - 4, nend = te.y0 + H + 3;
-    RowInS nx1 = load_row_s<FL>(d, Tin, rhog, vxg, vyg, nbeg, xg, pery, cvchi, lam_s);
-    RowInS nx2 = load_row_s<FL>(d, Tin, rhog, vxg, vyg, nbeg + 1, xg, pery, cvchi, lam_s);
+    RowInS nx1 = load_row_s<FL>(d, Tin, rhog, vxg, vyg, nbeg, xg, pery, lam_s);
+    RowInS nx2 = load_row_s<FL>(d, Tin, rhog, vxg, vyg, nbeg + 1, xg, pery, lam_s);
 #pragma unroll UNR
     for (int j = 0; j < H + 8; ++j) {
         const int n = nbeg + j;
         RowInS cur = nx1;
         nx1 = nx2;
-        if (n + 2 <= nend) nx2 = load_row_s<FL>(d, Tin, rhog, vxg, vyg, n + 2, xg, pery, cvchi, lam_s);
+        if (n + 2 <= nend) nx2 = load_row_s<FL>(d, Tin, rhog, vxg, vyg, n + 2, xg, pery, lam_s);
         // keep the loads of row n+2 here: the scheduler would otherwise sink
         // them next to their use to save registers and lose the prefetch
         __builtin_amdgcn_sched_barrier(0);
