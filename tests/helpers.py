@@ -48,3 +48,17 @@ def pool_case(nx, nyf, nys, superheat=0.1, n_spots=4, seed=0, y0=None, gamma_fra
     rho = W.layered_rho(nx, nyf, y0, d["rho_L"], d["rho_V"])
     T = W.thermal_init(nx, nys, nyf, d["Tsat"], Tb_row)
     return P, d, bc, rho, T
+
+
+def c1_case(case, superheat):
+    """The paper-scale long-run case of a stored record: `case` holds nx, nyf,
+    nys, seed, y0 and n_spots (spot trigger) or, with trigger "fluctuation",
+    a uniform T_b replaced by the seeded per-column T_b (1 + rel xi_x) for
+    t0 <= t < t1 (the workload's +-1% fluctuation)."""
+    fluct = case.get("trigger") == "fluctuation"
+    P, d, bc, rho, T = pool_case(case["nx"], case["nyf"], case["nys"], superheat=superheat,
+                                 n_spots=0 if fluct else case["n_spots"], seed=case["seed"], y0=case["y0"])
+    if fluct:
+        bc.update(Tb_alt=W.fluct_Tb(case["nx"], bc["Tb"][0], case["seed"], rel=case["rel"]),
+                  t0=case["t0"], t1=case["t1"])
+    return P, d, bc, rho, T
