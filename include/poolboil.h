@@ -57,9 +57,13 @@ enum {
     PB_ESTATE = -5       /* call not valid in the current state          */
 };
 
-/* Storage precision of the populations.  Arithmetic is FP64 in both modes.
- * PB_FP32_DEV stores f*_i - w_i rho(x) in FP32 (rho is the node's density,
- * kept in FP64); T, rho and v stay FP64. */
+/* Storage precision.  PB_FP64: everything FP64.  PB_FP32_DEV stores
+ * f*_i - w_i rho(x) in FP32 (rho is the node's density, kept in FP64) and v in
+ * FP32; T and rho stay FP64.  The flow step computes in FP64 in both modes;
+ * with PB_FP32_DEV the energy equation computes its operator and stages in
+ * FP32 as increments over the FP64 T (FP64 for the EOS derivative, the
+ * differences T(x + e_i) - T(x) and the update), within the FP32 tolerance
+ * of the oracle comparisons. */
 enum { PB_FP64 = 0, PB_FP32_DEV = 1 };
 
 /* Configuration flags (pb_config.flags). */
