@@ -174,7 +174,8 @@ def serving_legs(log):
     (heater 1/20 of the height), superheat U[0.02, 0.30] Tc, 20000 steps, all
     submitted at once; (2) a Poisson stream of 48 jobs, sizes 64..2048 x
     64..1024, 5000-20000 steps, arrival rate 4 jobs/s.  FP32-deviation
-    continuous batching against FP64 one job at a time, same jobs.  Tile shapes
+    continuous batching against FP64 one job at a time, same jobs (the curve
+    also FP32 one job at a time, to separate batching from precision).  Tile shapes
     for each precision come from the batch autotuner run on the curve's job
     mix (outside the timed legs)."""
     import numpy as np
@@ -190,11 +191,14 @@ def serving_legs(log):
         log(f"serving: tiles for precision {prec}: flow {tiles[prec]['tile']}, thermal {tiles[prec]['thermal_tile']}")
     log("serving: boiling curve, 32 jobs, FP32 batched")
     b32, q32 = _serve_jobs(curve, 1, True, 64, 32 << 30, realtime=False, tiles=tiles[1])
+    log("serving: boiling curve, 32 jobs, FP32 one at a time")
+    b32s, _ = _serve_jobs(curve, 1, False, 1, 32 << 30, realtime=False, tiles=tiles[1])
     log("serving: boiling curve, 32 jobs, FP64 one at a time")
     b64, q64 = _serve_jobs(curve, 0, False, 1, 32 << 30, realtime=False, tiles=tiles[0])
     dq = np.abs(np.array(q32) - np.array(q64)) / np.maximum(np.abs(np.array(q64)), 1e-30)
-    out["boiling_curve"] = dict(fp32_batched=b32, fp64_one_at_a_time=b64,
+    out["boiling_curve"] = dict(fp32_batched=b32, fp32_one_at_a_time=b32s, fp64_one_at_a_time=b64,
                                 speedup_jobs_per_hour=round(b32["jobs_per_hour"] / b64["jobs_per_hour"], 2),
+                                batching_gain_fp32=round(b32["jobs_per_hour"] / b32s["jobs_per_hour"], 2),
                                 mean_job_fluid_node_updates=float(np.mean([j["nx"] * j["nyf"] * j["steps"]
                                                                            for j in curve])),
                                 heat_flux_rel_diff_median=float(np.median(dq)), heat_flux_rel_diff_max=float(dq.max()),
