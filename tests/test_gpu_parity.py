@@ -40,15 +40,17 @@ def test_pool_boiling_100x100_200_steps(precision, tile):
     assert g["flux"]["n_samples"] == o["flux"]["n_samples"] == 16
 
 
-def test_ragged_domain_and_tile_shapes_are_bit_identical():
+@pytest.mark.parametrize("precision", [0, 1])
+def test_ragged_domain_and_tile_shapes_are_bit_identical(precision):
     """77x45 fluid over 5 heater rows (ragged against every tile shape): the
     result matches the oracle and is bit-identical for every flow tile and
-    every thermal variant."""
+    every thermal variant (strip heights 16 and 20 have strips inside the
+    fluid, which take the specialised path; 24 and 28 have none)."""
     P, d, bc, rho, T = pool_case(77, 45, 5, superheat=0.2, n_spots=3, seed=7, y0=17)
     ref = None
     shapes = [(64, 4), (64, 8), (32, 8), (128, 4), (32, 16), (64, 16), (64, 4)]
     for i, tile in enumerate(shapes):
-        g = gpu_domain(P, bc, rho, T, 0, tile=tile, thermal_tile=i % 4)
+        g = gpu_domain(P, bc, rho, T, precision, tile=tile, thermal_tile=i % 4)
         g.step(120)
         g.sync()
         r = g.read()
@@ -58,16 +60,16 @@ def test_ragged_domain_and_tile_shapes_are_bit_identical():
             o = oracle_domain(P, bc, rho, T)
             o.step(120)
             errs = compare(r, o.read())
-            _report("ragged", errs)
-            assert all(v <= 1e-11 for v in errs.values()), errs
+            _report(f"ragged precision={precision}", errs)
+            assert all(v <= TOL[precision] for v in errs.values()), errs
         else:
             for k in ("rho", "ux", "uy", "T", "f"):
                 np.testing.assert_array_equal(r[k], ref[k], err_msg=f"{k} differs for tile {tile}")
 
 
-@pytest.mark.parametrize("tile", [(0, 0), (32, 16)])
-@pytest.mark.parametrize("isothermal", [1, 0])
-def test_periodic_drop(isothermal, tile):
+@pytest.mark.parametrize("tile,isothermal,precision", [((0, 0), 1, 0), ((32, 16), 1, 0), ((0, 0), 0, 0),
+                                                       ((32, 16), 0, 0), ((0, 0), 0, 1)])
+def test_periodic_drop(isothermal, tile, precision):
     """Fully periodic box with a drop (no walls, no heater): exercises the
     periodic wrap in y of streaming, forces and the thermal stencil."""
     nx, ny = 48, 40
@@ -75,10 +77,10 @@ def test_periodic_drop(isothermal, tile):
     rho = W.drop_rho(nx, ny, 9.0, d["rho_L"], d["rho_V"], width=3.0, cx=20.3, cy=17.6)
     T = W.perturbed(np.full((ny, nx), d["Tsat"]), 0.02, 11)
     bc = dict(T_top=d["Tsat"])
-    g, o = run_pair(P, bc, rho, T, steps=200, precision=0, tile=tile)
+    g, o = run_pair(P, bc, rho, T, steps=200, precision=precision, tile=tile)
     errs = compare(g, o)
-    _report(f"drop iso={isothermal} tile={tile}", errs)
-    assert all(v <= 1e-11 for v in errs.values()), errs
+    _report(f"drop iso={isothermal} tile={tile} precision={precision}", errs)
+    assert all(v <= TOL[precision] for v in errs.values()), errs
 
 
 def test_frozen_flow_conduction():
