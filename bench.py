@@ -148,6 +148,43 @@ def cpu_baseline(nx, nyf, nys, steps):
                        f"{dt:.1f} s")
 
 
+def small_configs(log):
+    """Single-domain rates of the smaller set-ups (one domain per launch, so
+    launch overhead shows): the 100x100 + 100x10 pool in FP64 and the
+    400x400 + 400x20 paper-scale pool in both storage modes; 4 hot spots / 6
+    hot spots, superheat 0.1 Tc.  (The oracle's rate on the 100x100 pool is in
+    the cpu_baseline leg.)  Each is timed with plain launches and as a batch of
+    one replayed from captured graphs of 100 steps."""
+    from paper_1911_10747_amd import poolboil as pb, presets
+    out = {}
+    for name, nx, nyf, nys, prec, spc, steps in (("pool_100x100+10_fp64", 100, 100, 10, 0, 25, 4000),
+                                                 ("pool_400x400+20_fp32dev", 400, 400, 20, 1, 67, 4000),
+                                                 ("pool_400x400+20_fp64", 400, 400, 20, 0, 67, 4000)):
+        spec = presets.JobSpec(nx=nx, nyf=nyf, nys=nys, superheat=0.1, steps=steps, precision=prec,
+                               spots_per_columns=spc)
+        rates = []
+        for graph in (False, True):
+            dom = presets.make_domain(spec, with_window=False)
+            b = pb.Batch([dom], steps_per_graph=100) if graph else None
+            stepper = b if graph else dom
+            stepper.step(200)
+            dom.sync()
+            t0 = time.perf_counter()
+            stepper.step(steps)
+            dom.sync()
+            rates.append(time.perf_counter() - t0)
+            if b is not None:
+                b.close()
+            dom.close()
+        out[name] = dict(gpu_mlups=round(nx * nyf * steps / rates[0] / 1e6, 1),
+                         gpu_mlups_graph_replay=round(nx * nyf * steps / rates[1] / 1e6, 1),
+                         ms_per_step=round(rates[0] / steps * 1e3, 4),
+                         ms_per_step_graph_replay=round(rates[1] / steps * 1e3, 4), steps=steps)
+        log(f"small configs: {name}: {out[name]['gpu_mlups']} MLUPS, "
+            f"{out[name]['gpu_mlups_graph_replay']} with graph replay")
+    return out
+
+
 def _serve_jobs(jobs, precision, batching, max_slots, mem_budget, realtime, time_scale=1.0, tiles=None):
     from paper_1911_10747_amd import presets, serve
     tile, tv = (tiles["tile"], tiles["thermal_tile"]) if tiles else ((0, 0), 0)
@@ -321,9 +358,12 @@ def main():
     dom.close()
     if not args.no_serving:
         out["serving"] = serving_legs(lambda m: print("bench: " + m, file=sys.stderr, flush=True))
+        out["small_configs"] = small_configs(lambda m: print("bench: " + m, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         print(f"bench: oracle on {args.cpu_steps} steps", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(nx, nyf, nys, args.cpu_steps)
+        if "small_configs" in out:
+            out["cpu_baseline"]["pool_100x100+10"] = cpu_baseline(100, 100, 10, 200)
         if "serving" in out:
             # the same boiling-curve jobs on the oracle, one job per host core
             bc = out["serving"]["boiling_curve"]
