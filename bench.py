@@ -187,7 +187,9 @@ def small_configs(log):
 
 def _serve_jobs(jobs, precision, batching, max_slots, mem_budget, realtime, time_scale=1.0, tiles=None):
     from paper_1911_10747_amd import presets, serve
-    tile, tv = (tiles["tile"], tiles["thermal_tile"]) if tiles else ((0, 0), 0)
+    # batched runs take the shapes tuned on the batched mix; a job run alone
+    # takes the library's choice for its own size (thermal_tile 0)
+    tile, tv = (tiles["tile"], tiles["thermal_tile"]) if (tiles and batching) else ((0, 0), 0)
     srv = serve.Server(mem_budget=mem_budget, max_slots=max_slots, precision=precision, chunk_steps=2000,
                        graph_steps=100 if batching else 0, batching=batching, tile=tile, thermal_tile=tv)
     if realtime:
@@ -212,26 +214,25 @@ def serving_legs(log):
     submitted at once; (2) a Poisson stream of 48 jobs, sizes 64..2048 x
     64..1024, 5000-20000 steps, arrival rate 4 jobs/s.  FP32-deviation
     continuous batching against FP64 one job at a time, same jobs (the curve
-    also FP32 one job at a time, to separate batching from precision).  Tile shapes
-    for each precision come from the batch autotuner run on the curve's job
-    mix (outside the timed legs)."""
+    also FP32 one job at a time, to separate batching from precision).  Batched
+    runs take the tile shapes of the batch autotuner run on the curve's job
+    mix (outside the timed legs); a job run alone takes the library's choice
+    for its size."""
     import numpy as np
     import workloads as W
     from paper_1911_10747_amd import autotune, presets
     out = {}
     curve = W.batch_jobs(seed=0, n=32, steps=20000)
-    tiles = {}
-    for prec in (1, 0):
-        specs = [presets.JobSpec(nx=j["nx"], nyf=j["nyf"], nys=j["nys"], superheat=j["superheat"], steps=j["steps"],
-                                 seed=j["seed"], precision=prec) for j in curve]
-        tiles[prec] = autotune.tune_batch(specs, log=log)
-        log(f"serving: tiles for precision {prec}: flow {tiles[prec]['tile']}, thermal {tiles[prec]['thermal_tile']}")
+    specs = [presets.JobSpec(nx=j["nx"], nyf=j["nyf"], nys=j["nys"], superheat=j["superheat"], steps=j["steps"],
+                             seed=j["seed"], precision=1) for j in curve]
+    tiles = autotune.tune_batch(specs, log=log)
+    log(f"serving: batched FP32 tiles: flow {tiles['tile']}, thermal {tiles['thermal_tile']}")
     log("serving: boiling curve, 32 jobs, FP32 batched")
-    b32, q32 = _serve_jobs(curve, 1, True, 64, 32 << 30, realtime=False, tiles=tiles[1])
+    b32, q32 = _serve_jobs(curve, 1, True, 64, 32 << 30, realtime=False, tiles=tiles)
     log("serving: boiling curve, 32 jobs, FP32 one at a time")
-    b32s, _ = _serve_jobs(curve, 1, False, 1, 32 << 30, realtime=False, tiles=tiles[1])
+    b32s, _ = _serve_jobs(curve, 1, False, 1, 32 << 30, realtime=False)
     log("serving: boiling curve, 32 jobs, FP64 one at a time")
-    b64, q64 = _serve_jobs(curve, 0, False, 1, 32 << 30, realtime=False, tiles=tiles[0])
+    b64, q64 = _serve_jobs(curve, 0, False, 1, 32 << 30, realtime=False)
     dq = np.abs(np.array(q32) - np.array(q64)) / np.maximum(np.abs(np.array(q64)), 1e-30)
     out["boiling_curve"] = dict(fp32_batched=b32, fp32_one_at_a_time=b32s, fp64_one_at_a_time=b64,
                                 speedup_jobs_per_hour=round(b32["jobs_per_hour"] / b64["jobs_per_hour"], 2),
@@ -242,13 +243,12 @@ def serving_legs(log):
                                 within_3pct=int((dq <= 0.03).sum()))
     stream = W.job_stream(seed=0, n=48, rate_per_s=4.0)
     log("serving: Poisson stream, 48 jobs, FP32 continuous batching")
-    s32, q32 = _serve_jobs(stream, 1, True, 32, 4 << 30, realtime=True, tiles=tiles[1])
+    s32, q32 = _serve_jobs(stream, 1, True, 32, 4 << 30, realtime=True, tiles=tiles)
     log("serving: Poisson stream, 48 jobs, FP64 one at a time")
-    s64, q64 = _serve_jobs(stream, 0, False, 1, 4 << 30, realtime=True, tiles=tiles[0])
+    s64, q64 = _serve_jobs(stream, 0, False, 1, 4 << 30, realtime=True)
     dq = np.abs(np.array(q32) - np.array(q64)) / np.maximum(np.abs(np.array(q64)), 1e-30)
-    out["tiles"] = {("fp32_deviation" if p else "fp64"): dict(flow=list(t["tile"]), thermal=t["thermal_tile"],
-                                                            ms_per_step_curve_mix=round(t["ms_per_step"], 4))
-                    for p, t in tiles.items()}
+    out["batched_tiles"] = dict(flow=list(tiles["tile"]), thermal=tiles["thermal_tile"],
+                                ms_per_step_curve_mix=round(tiles["ms_per_step"], 4))
     out["poisson_stream"] = dict(rate_jobs_per_s=4.0, fp32_batched=s32, fp64_one_at_a_time=s64,
                                  heat_flux_rel_diff_median=float(np.median(dq)),
                                  heat_flux_rel_diff_max=float(dq.max()), within_3pct=int((dq <= 0.03).sum()))

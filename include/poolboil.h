@@ -86,7 +86,11 @@ typedef struct pb_config {
     int32_t tile_x, tile_y;          /* flow-kernel tile: 64x4, 64x8, 32x8,       */
                                      /* 128x4, 32x16 or 64x16 nodes; 0,0 = 64x8;  */
                                      /* every tile gives the same bits           */
-    int32_t thermal_tile;            /* thermal-kernel tile variant; 0 = default */
+    int32_t thermal_tile;            /* energy-equation strips of 56 columns by */
+                                     /* 28, 20, 24, 16, 12 or 8 rows (1..6);     */
+                                     /* 0 = chosen from the domain size (tall    */
+                                     /* strips for large domains, short ones for */
+                                     /* small); every variant gives the same bits */
     double a, b, R, omega, Tc;       /* Eq. 13 (Tc explicit)                     */
     double G;                        /* Eq. 11-12 interaction strength (< 0)     */
     double s_e, s_q, varpi;          /* Eq. 3: s1 = s2 = s_e, s4 = s6 = s_q; Eq. 9 */

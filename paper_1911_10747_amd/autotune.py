@@ -15,7 +15,7 @@ from . import poolboil as pb
 from . import presets
 
 FLOW_TILES = [(64, 4), (64, 8), (32, 8), (128, 4), (32, 16), (64, 16)]
-THERMAL_VARIANTS = list(range(4))
+THERMAL_VARIANTS = list(range(1, 7))   # config values: strips of 28, 20, 24, 16, 12, 8 rows (0 = by size)
 CACHE = os.environ.get("POOLBOIL_TUNE_CACHE", os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                             "tune_cache.json"))
 
@@ -115,8 +115,8 @@ def tune_batch(specs, steps=300, warmup=50, steps_per_graph=100, log=None):
         if log:
             log(f"autotune batch of {len(specs)}: flow tile {tile}: {flow[tile]:.4f} ms/step")
     best_tile = min(flow, key=flow.get)
-    therm = {0: flow[best_tile]}
-    for v in THERMAL_VARIANTS[1:]:
+    therm = {}
+    for v in THERMAL_VARIANTS:
         therm[v] = _time_batch(with_tiles(best_tile, v), steps, warmup, steps_per_graph)
         if log:
             log(f"autotune batch of {len(specs)}: thermal variant {v}: {therm[v]:.4f} ms/step")

@@ -55,6 +55,30 @@ int flow_variant_of(const pb_config &c) {
 
 int ntiles_for(int nx, int ny, int bx, int by) { return ((nx + bx - 1) / bx) * ((ny + by - 1) / by); }
 
+// Thermal strip variant of a config: thermal_tile k >= 1 is variant k - 1;
+// 0 lets the library choose from the domain size: the tallest strips that
+// still give about one strip per SIMD slot (3072 at 3 waves per SIMD on 256
+// CUs), else the shortest, since a small domain's step time is the sweep of
+// one strip.
+int thermal_variant_of(const pb_config &c) {
+    if (c.thermal_tile > 0) return c.thermal_tile - 1;
+    const int nr = c.ny_fluid + c.ny_solid;
+    int best = -1, best_h = 0, shortest = 0, shortest_h = 1 << 30;
+    for (int v = 0; v < pb_thermal_variants(); ++v) {
+        int bx, by;
+        pb_thermal_tile_shape(v, &bx, &by);
+        if (ntiles_for(c.nx, nr, bx, by) >= 3072 && by > best_h) {
+            best = v;
+            best_h = by;
+        }
+        if (by < shortest_h) {
+            shortest = v;
+            shortest_h = by;
+        }
+    }
+    return best >= 0 ? best : shortest;
+}
+
 int max_tiles(int nx, int ny, bool flow) {
     int m = 0, nv = flow ? pb_flow_variants() : pb_thermal_variants();
     for (int v = 0; v < nv; ++v) {
@@ -119,7 +143,7 @@ int validate(const pb_config *c) {
         return fail(PB_EINVAL, "relaxation rates must lie in (0, 2)");
     if (!(c->tau_L > 0.5) || !(c->tau_V > 0.5)) return fail(PB_EINVAL, "relaxation times must exceed 1/2");
     if (flow_variant_of(*c) < 0) return fail(PB_EINVAL, "no flow tile %dx%d", c->tile_x, c->tile_y);
-    if (c->thermal_tile < 0 || c->thermal_tile >= pb_thermal_variants())
+    if (c->thermal_tile < 0 || c->thermal_tile > pb_thermal_variants())
         return fail(PB_EINVAL, "no thermal tile variant %d", c->thermal_tile);
     return PB_OK;
 }
@@ -286,7 +310,7 @@ int pb_create_domain(const pb_config *cfg, void *stream, void *dev_mem, size_t d
     d->pitch = (int)align_up((size_t)cfg->nx, 64);
     d->nr = cfg->ny_fluid + cfg->ny_solid;
     d->fvar = flow_variant_of(*cfg);
-    d->tvar = cfg->thermal_tile;
+    d->tvar = thermal_variant_of(*cfg);
     if (dev_mem) {
         if (dev_bytes < d->L.total) {
             delete d;
