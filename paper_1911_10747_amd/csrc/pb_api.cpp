@@ -201,7 +201,7 @@ struct pb_batch {
     PbTile *dtiles_flow = nullptr, *dtiles_th = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
-    bool any_flux = true;
+    std::vector<char> graph_flux;   // steps of the captured graph that launch the flux sample
     bool owns_stream = false;
     hipEvent_t ev_batch = nullptr, ev_dom = nullptr;
     std::vector<hipStream_t> dom_streams;   // distinct member streams
@@ -734,7 +734,27 @@ int pb_batch_create(pb_domain *const *doms, int32_t n, int32_t steps_per_graph, 
     return PB_OK;
 }
 
-static int batch_enqueue(pb_batch *b, int nsteps) {
+// Which of the next nsteps steps (step k ends at t + k + 1) some member
+// samples for the heat flux.  The flux kernel checks each domain's window and
+// period itself, so a launch where none samples only costs its dispatch; a
+// missing one would lose samples.  For a captured graph (periodic = true)
+// the steps must hold for every replay, which holds when the graph length is
+// a multiple of each period; else every step launches.
+static std::vector<char> batch_flux_steps(const pb_batch *b, int nsteps, bool periodic) {
+    std::vector<char> need(nsteps, 0);
+    for (const pb_domain *d : b->doms) {
+        if (!(d->hd.fl_tb > d->hd.fl_ta && d->cfg.ny_solid >= 1)) continue;
+        const int64_t e = std::max<int64_t>(1, d->hd.fl_every);
+        if (periodic && nsteps % e != 0) return std::vector<char>(nsteps, 1);
+        for (int k = 0; k < nsteps; ++k) {
+            const int64_t r = (d->t + k + 1 - d->hd.fl_ta) % e;
+            if (r == 0) need[k] = 1;
+        }
+    }
+    return need;
+}
+
+static int batch_enqueue(pb_batch *b, int nsteps, const std::vector<char> &flux) {
     const PbDesc *const *dp = (const PbDesc *const *)b->dptrs;
     const int nd = (int)b->doms.size();
     for (int k = 0; k < nsteps; ++k) {
@@ -743,7 +763,7 @@ static int batch_enqueue(pb_batch *b, int nsteps) {
                                   b->stream));
         if (b->nt_th > 0)
             PB_HIP(pb_launch_thermal(b->prec, b->tvar, dp, b->dtiles_th, b->nt_th, b->grid_th, k, b->stream));
-        if (b->any_flux) PB_HIP(pb_launch_flux(dp, nd, k, b->stream));
+        if (flux[k]) PB_HIP(pb_launch_flux(dp, nd, k, b->stream));
     }
     PB_HIP(pb_launch_advance(b->dptrs, nd, nsteps, b->stream));
     return PB_OK;
@@ -752,11 +772,6 @@ static int batch_enqueue(pb_batch *b, int nsteps) {
 int pb_batch_step(pb_batch *b, int64_t n) {
     if (!b) return fail(PB_EINVAL, "batch is NULL");
     if (n < 0) return fail(PB_EINVAL, "n must be >= 0");
-    // descriptors must match the host mirrors before device-side advancing
-    b->any_flux = false;
-    for (pb_domain *d : b->doms) {
-        if (d->hd.fl_tb > d->hd.fl_ta && d->cfg.ny_solid >= 1) b->any_flux = true;
-    }
     int rc;
     // the batch stream starts after the work already queued on member streams
     for (hipStream_t s : b->dom_streams) {
@@ -766,14 +781,24 @@ int pb_batch_step(pb_batch *b, int64_t n) {
     }
     while (n > 0) {
         if (b->spg > 0 && n >= b->spg) {
+            // a member's flux window or phase changed since the capture: capture again
+            const std::vector<char> flux = batch_flux_steps(b, b->spg, true);
+            if (b->gexec && flux != b->graph_flux) {
+                PB_HIP(hipStreamSynchronize(b->stream));
+                PB_HIP(hipGraphExecDestroy(b->gexec));
+                PB_HIP(hipGraphDestroy(b->graph));
+                b->gexec = nullptr;
+                b->graph = nullptr;
+            }
             if (!b->gexec) {
                 PB_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-                rc = batch_enqueue(b, b->spg);
+                rc = batch_enqueue(b, b->spg, flux);
                 hipGraph_t g = nullptr;
                 hipError_t e = hipStreamEndCapture(b->stream, &g);
                 if (rc) return rc;
                 if (e != hipSuccess) return fail(PB_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
                 b->graph = g;
+                b->graph_flux = flux;
                 PB_HIP(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
             }
             PB_HIP(hipGraphLaunch(b->gexec, b->stream));
@@ -786,7 +811,7 @@ int pb_batch_step(pb_batch *b, int64_t n) {
             n -= b->spg;
         } else {
             const int m = (int)std::min<int64_t>(n, 1 << 20);
-            if ((rc = batch_enqueue(b, m))) return rc;
+            if ((rc = batch_enqueue(b, m, batch_flux_steps(b, m, false)))) return rc;
             for (pb_domain *d : b->doms) {
                 d->t += m;
                 d->par ^= (m & 1);

@@ -241,6 +241,41 @@ def test_batch_matches_alone_bit_exact(precision):
         g.close()
 
 
+def test_batch_flux_windows_set_between_graph_replays():
+    """Heat-flux windows opened on batch members after the batch has captured
+    and replayed its step graph, with sampling periods that do (5) and do not
+    (3) divide the graph length and different phases: every member's samples
+    and means equal those of the same domain stepped alone."""
+    from paper_1911_10747_amd import poolboil as pb
+    cases = [pool_case(70, 50, 4, superheat=0.08, seed=1), pool_case(33, 20, 3, superheat=0.25, seed=2),
+             pool_case(130, 64, 7, superheat=0.15, seed=3)]
+    windows = [(23, 1000, 5), (31, 1000, 3), (27, 60, 5)]
+    alone = []
+    for (P, d, bc, rho, T), w in zip(cases, windows):
+        g = gpu_domain(P, bc, rho, T, 1)
+        g.step(20)
+        g.flux_window(*w)
+        g.step(55)
+        g.sync()
+        alone.append(g.heat_flux())
+        g.close()
+    doms = [gpu_domain(P, bc, rho, T, 1) for P, d, bc, rho, T in cases]
+    batch = pb.Batch(doms, steps_per_graph=10)
+    batch.step(20)                      # two replays of a graph with no flux sample
+    for g, w in zip(doms, windows):
+        g.flux_window(*w)
+    batch.step(55)                      # captured again: five replays + 5 eager steps
+    for g, f0 in zip(doms, alone):
+        g.sync()
+        f = g.heat_flux()
+        print("flux", f["n_samples"], f0["n_samples"], flush=True)
+        assert f["n_samples"] > 0
+        assert f == f0
+    batch.close()
+    for g in doms:
+        g.close()
+
+
 @pytest.mark.parametrize("persistent", [1, 5, 64])
 def test_persistent_batch_grid(persistent):
     """A capped (persistent) grid whose blocks loop over the tile work-list of
