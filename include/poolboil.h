@@ -132,6 +132,13 @@ typedef struct pb_batch pb_batch;
  * flags and flux accumulators; read-back staging is allocated on first read). */
 int pb_domain_bytes(const pb_config *cfg, size_t *bytes);
 
+/* Rows of the energy-equation strips (56 columns wide, Eqs. 24-28 swept upwards
+ * by one wavefront each) a domain with this configuration uses: the explicit
+ * thermal_tile, or for thermal_tile = 0 the tallest strips that still give
+ * about 3072 strips (one per SIMD slot), else the shortest.  Host only;
+ * PB_EINVAL for an invalid configuration. */
+int pb_thermal_strip_rows(const pb_config *cfg, int *rows);
+
 /* Create a domain.  stream: a hipStream_t (NULL = the null stream).  dev_mem:
  * NULL to let the library allocate, or caller-owned device memory of at least
  * pb_domain_bytes() bytes (256-byte aligned) that must outlive the domain.

@@ -289,6 +289,16 @@ extern "C" {
 int pb_version(void) { return PB_VERSION; }
 const char *pb_last_error(void) { return g_err.c_str(); }
 
+int pb_thermal_strip_rows(const pb_config *cfg, int *rows) {
+    int rc = validate(cfg);
+    if (rc) return rc;
+    if (!rows) return fail(PB_EINVAL, "rows is NULL");
+    int bx, by;
+    pb_thermal_tile_shape(thermal_variant_of(*cfg), &bx, &by);
+    *rows = by;
+    return PB_OK;
+}
+
 int pb_domain_bytes(const pb_config *cfg, size_t *bytes) {
     int rc = validate(cfg);
     if (rc) return rc;

@@ -18,7 +18,7 @@ PB_FP64, PB_FP32_DEV = 0, 1
 PB_PERIODIC_Y, PB_ISOTHERMAL, PB_FROZEN_FLOW, PB_SBAR2_PLUS, PB_VARPI_FM_ONLY = 0x1, 0x2, 0x4, 0x8, 0x10
 
 EXPORTED = [
-    "pb_domain_bytes", "pb_create_domain", "pb_destroy_domain", "pb_set_bc", "pb_set_fields", "pb_set_fields_full",
+    "pb_domain_bytes", "pb_thermal_strip_rows", "pb_create_domain", "pb_destroy_domain", "pb_set_bc", "pb_set_fields", "pb_set_fields_full",
     "pb_step", "pb_sync", "pb_read_fields", "pb_flux_window", "pb_heat_flux", "pb_profile_steps", "pb_time",
     "pb_rho_bar",
     "pb_batch_create", "pb_batch_step", "pb_batch_destroy", "pb_eos_critical_temperature", "pb_eos_coexistence",
@@ -80,6 +80,7 @@ def _load():
     vp, dp, i64, i32 = C.c_void_p, C.POINTER(C.c_double), C.c_int64, C.c_int32
     sig = {
         "pb_domain_bytes": ([C.POINTER(Config), C.POINTER(C.c_size_t)], C.c_int),
+        "pb_thermal_strip_rows": ([C.POINTER(Config), C.POINTER(C.c_int)], C.c_int),
         "pb_create_domain": ([C.POINTER(Config), vp, vp, C.c_size_t, C.POINTER(vp)], C.c_int),
         "pb_destroy_domain": ([vp], None),
         "pb_set_bc": ([vp, C.POINTER(BC)], C.c_int),
@@ -143,6 +144,12 @@ def make_config(**kw):
 def domain_bytes(cfg):
     n = C.c_size_t()
     _check(lib.pb_domain_bytes(C.byref(cfg), C.byref(n)))
+    return n.value
+
+
+def thermal_strip_rows(cfg):
+    n = C.c_int()
+    _check(lib.pb_thermal_strip_rows(C.byref(cfg), C.byref(n)))
     return n.value
 
 
