@@ -68,7 +68,7 @@ class Flux(C.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() (no fallback exists)")
+        raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_1911_10747_amd._build (no fallback exists)")
     # torch bundles its own HIP runtime under a different file name; loading it
     # first makes the library bind to that same runtime (one runtime per
     # process, so torch-allocated device memory is valid for the library)
