@@ -47,12 +47,23 @@ def algorithmic_bytes(nx, nyf, nys, precision):
 TRAFFIC_FILES = {"roofline": "pmc_traffic_step_4096x2048_fp32dev.txt"}
 
 
+def source_sha256():
+    """Hash of the kernels and of the host library that builds their work
+    lists (both decide what a launch reads and writes)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1911_10747_amd", "csrc")
+    h = hashlib.sha256()
+    for name in ("pb_kernels.hip", "pb_api.cpp"):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def load_profile(workload):
     """Per-step HBM bytes (both launches) and per-kernel bytes and wavefront
     VALU instructions, measured with rocprofv3 (FETCH_SIZE / WRITE_SIZE scaled
     by a copy-kernel calibration, SQ_INSTS_VALU), if the measurement was taken
-    on the current kernel source (hash match); else None."""
-    import hashlib
+    on the current kernel and host-library source (hash match); else None."""
     if workload not in TRAFFIC_FILES:
         return None
     path = os.path.join(ROOT, "profiles", TRAFFIC_FILES[workload])
@@ -60,8 +71,7 @@ def load_profile(workload):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    src = open(os.path.join(ROOT, "paper_1911_10747_amd", "csrc", "pb_kernels.hip"), "rb").read()
-    if rec.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+    if rec.get("source_sha256") != source_sha256():
         return None
     return rec
 

@@ -42,7 +42,8 @@ struct PbDesc {
 };
 
 struct PbTile {
-    int32_t dom, x0, y0, pad;
+    int32_t dom, x0, y0;
+    int32_t short_strip;  // energy sweep: 1 = an 8-row strip, whatever the launch's strip height
 };
 
 enum { PB_MODE_STEP = 0, PB_MODE_READ = 1 };

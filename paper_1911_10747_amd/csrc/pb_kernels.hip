@@ -1012,6 +1012,22 @@ __device__ __forceinline__ void thermal_strip_sp(cdesc &d, const PbTile &te, int
     if (bad) flag_error(d);
 }
 
+// One strip of H rows: the specialised path where every row it reads is a
+// fluid row, else the general one.
+template <typename VT, int H, int UNR>
+__device__ __forceinline__ void thermal_tile(cdesc &d, const PbTile &te, int k, int lane) {
+    const bool fl = !(d.flags & F_PERY) && te.y0 - 4 >= d.nys && te.y0 + H + 3 < d.nr;
+    if constexpr (std::is_same<VT, float>::value) {
+        if (fl) thermal_strip_sp<H, UNR, true>(d, te, k, lane);
+        else thermal_strip_sp<H, UNR, false>(d, te, k, lane);
+    } else {
+        if (fl) thermal_strip<VT, H, UNR, true>(d, te, k, lane);
+        else thermal_strip<VT, H, UNR, false>(d, te, k, lane);
+    }
+}
+
+// A tile with short_strip set is an 8-row strip: the work-list ends with such strips
+// so that the last wavefronts to start are short ones.
 template <typename VT, int H, int WPE, int UNR>
 __global__ __launch_bounds__(64, WPE) void k_thermal_sweep(const PbDesc *const *__restrict__ dps,
                                                             const PbTile *__restrict__ tiles, int ntiles, int k) {
@@ -1019,14 +1035,8 @@ __global__ __launch_bounds__(64, WPE) void k_thermal_sweep(const PbDesc *const *
     for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
         const PbTile te = tiles[tl];
         cdesc &d = *(const PbDesc PB_CAS *)dps[te.dom];
-        const bool fl = !(d.flags & F_PERY) && te.y0 - 4 >= d.nys && te.y0 + H + 3 < d.nr;
-        if constexpr (std::is_same<VT, float>::value) {
-            if (fl) thermal_strip_sp<H, UNR, true>(d, te, k, lane);
-            else thermal_strip_sp<H, UNR, false>(d, te, k, lane);
-        } else {
-            if (fl) thermal_strip<VT, H, UNR, true>(d, te, k, lane);
-            else thermal_strip<VT, H, UNR, false>(d, te, k, lane);
-        }
+        if (te.short_strip) thermal_tile<VT, 8, 16>(d, te, k, lane);
+        else thermal_tile<VT, H, UNR>(d, te, k, lane);
     }
 }
 

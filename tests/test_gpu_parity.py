@@ -67,6 +67,27 @@ def test_ragged_domain_and_tile_shapes_are_bit_identical(precision):
                 np.testing.assert_array_equal(r[k], ref[k], err_msg=f"{k} differs for tile {tile}")
 
 
+@pytest.mark.parametrize("precision,nx,nyf,nys", [(0, 3590, 1403, 56), (1, 4096, 1800, 64)])
+def test_short_tail_strips_bit_identical(precision, nx, nyf, nys):
+    """Domains with enough 28-row energy strips that the library ends the work
+    list with 8-row strips (more than 1.5x the 2048 / 3072 wavefront slots of
+    the FP64 / FP32 sweep; ragged columns and a ragged top strip): 20 steps
+    give the same bits as strips of 8 rows throughout (thermal_tile 6), which
+    the ragged-domain test holds to the oracle."""
+    from paper_1911_10747_amd import poolboil as pb
+    P, d, bc, rho, T = pool_case(nx, nyf, nys, superheat=0.15, n_spots=nx // 64, seed=3, y0=int(0.4 * nyf))
+    assert pb.thermal_strip_rows(pb_config(P, precision, (64, 8), 1)) == 28
+    out = []
+    for tt in (1, 6):
+        g = gpu_domain(P, bc, rho, T, precision, tile=(64, 8), thermal_tile=tt)
+        g.step(20)
+        g.sync()
+        out.append(g.read(with_f=False))
+        g.close()
+    for k in ("rho", "ux", "uy", "T"):
+        np.testing.assert_array_equal(out[0][k], out[1][k], err_msg=f"{k} differs")
+
+
 @pytest.mark.parametrize("tile,isothermal,precision", [((0, 0), 1, 0), ((32, 16), 1, 0), ((0, 0), 0, 0),
                                                        ((32, 16), 0, 0), ((0, 0), 0, 1)])
 def test_periodic_drop(isothermal, tile, precision):
