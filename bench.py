@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     # name: (nx, nyf, nys, precision, description)
     "roofline": (4096, 2048, 64, 1, "pool boiling 4096x2048 fluid + 4096x64 heater, FP32-deviation populations, "
-                                    "FP64 flow/EOS/T/rho, FP32 energy-equation increments, 1 hot spot per 64 "
+                                    "FP64 flow/EOS/T, FP32 rho, FP32 energy-equation increments, 1 hot spot per 64 "
                                     "columns, superheat 0.1 Tc"),
     "roofline_fp64": (4096, 2048, 64, 0, "pool boiling 4096x2048 fluid + 4096x64 heater, FP64 populations, "
                                          "1 hot spot per 64 columns, superheat 0.1 Tc"),

@@ -57,9 +57,11 @@ enum {
     PB_ESTATE = -5       /* call not valid in the current state          */
 };
 
-/* Storage precision.  PB_FP64: everything FP64.  PB_FP32_DEV stores
- * f*_i - w_i rho(x) in FP32 (rho is the node's density, kept in FP64) and v in
- * FP32; T and rho stay FP64.  The flow step computes in FP64 in both modes;
+/* Storage precision.  PB_FP64: everything FP64.  PB_FP32_DEV stores rho(x)
+ * and v in FP32 and the populations as f*_i - w_i rho(x) in FP32, taken
+ * against that stored FP32 density, so rebuilding f in FP64 on load is exact
+ * up to the rounding of the deviation; T stays FP64.  The flow step (moments,
+ * psi and the EOS, forces, collision) computes in FP64 in both modes;
  * with PB_FP32_DEV the energy equation computes its operator and stages in
  * FP32 as increments over the FP64 T (FP64 for the EOS derivative, the
  * differences T(x + e_i) - T(x) and the update), within the FP32 tolerance

@@ -105,8 +105,8 @@ Layout layout_of(const pb_config &c) {
     L.dptr = take(sizeof(void *));
     L.f[0] = take(9 * nf * es);
     L.f[1] = take(9 * nf * es);
-    L.rho[0] = take(nf * 8);
-    L.rho[1] = take(nf * 8);
+    L.rho[0] = take(nf * es);   // density stored like the populations: FP64 or FP32
+    L.rho[1] = take(nf * es);
     L.vx = take(nf * es);   // velocity stored like the populations: FP64 or FP32
     L.vy = take(nf * es);
     L.T[0] = take(nt * 8);
@@ -295,7 +295,7 @@ int enqueue_steps(pb_domain *d, int64_t n) {
             if (!iso) PB_HIP(pb_launch_thermal(d->cfg.precision, d->tvar, dp, d->dtiles_th, d->nt_th, d->nt_th, k, d->stream));
             const int64_t tk = d->t + k + 1;
             if (sampling && tk >= d->hd.fl_ta && tk < d->hd.fl_tb && (tk - d->hd.fl_ta) % d->hd.fl_every == 0)
-                PB_HIP(pb_launch_flux(dp, 1, k, d->stream));
+                PB_HIP(pb_launch_flux(d->cfg.precision, dp, 1, k, d->stream));
         }
         PB_HIP(pb_launch_advance(d->dptr, 1, m, d->stream));
         d->t += m;
@@ -374,7 +374,7 @@ int pb_create_domain(const pb_config *cfg, void *stream, void *dev_mem, size_t d
     h.flags = cfg->flags;
     for (int b = 0; b < 2; ++b) {
         h.f[b] = d->base + L.f[b];
-        h.rho[b] = (double *)(d->base + L.rho[b]);
+        h.rho[b] = (void *)(d->base + L.rho[b]);
         h.T[b] = (double *)(d->base + L.T[b]);
     }
     h.vx = d->base + L.vx;
@@ -479,12 +479,14 @@ int pb_set_fields(pb_domain *d, const double *rho, const double *T) {
     d->t = 0;
     d->par = 0;
     d->hd.rho_bar = sum / ((double)nx * nyf);
-    if ((rc = copy_rows_h2d(d, d->hd.rho[0], rho, nyf))) return rc;
-    for (int b = 0; b < 2; ++b)
-        if ((rc = copy_rows_h2d(d, d->hd.T[b], Th.data(), d->nr))) return rc;
+    // the FP64 densities go through T[1] (nr >= nyf rows of the same pitch),
+    // which k_init reads before T is uploaded behind it on the same stream
+    if ((rc = copy_rows_h2d(d, d->hd.T[1], rho, nyf))) return rc;
     PB_HIP(hipMemsetAsync(d->hd.err, 0, sizeof(int32_t), d->stream));
     if ((rc = upload_desc(d))) return rc;
-    PB_HIP(pb_launch_init(d->cfg.precision, d->ddesc, 0, d->stream));
+    PB_HIP(pb_launch_init(d->cfg.precision, d->ddesc, d->hd.T[1], d->stream));
+    for (int b = 0; b < 2; ++b)
+        if ((rc = copy_rows_h2d(d, d->hd.T[b], Th.data(), d->nr))) return rc;
     PB_HIP(hipStreamSynchronize(d->stream));
     d->fields_set = true;
     return PB_OK;
@@ -525,17 +527,22 @@ int pb_set_fields_full(pb_domain *d, const double *f, const double *T, int64_t t
             if ((rc = copy_rows_h2d(d, (double *)d->hd.f[par] + (size_t)i * nyf * d->pitch, fs.data() + (size_t)i * np,
                                     nyf)))
                 return rc;
+        if ((rc = copy_rows_h2d(d, d->hd.rho[par], rref.data(), nyf))) return rc;
     } else {
-        std::vector<float> dev(9 * np);
+        // deviations against the density as stored (FP32)
+        std::vector<float> dev(9 * np), r32(np);
+        for (size_t n = 0; n < np; ++n) r32[n] = (float)rref[n];
         for (int i = 0; i < 9; ++i)
-            for (size_t n = 0; n < np; ++n) dev[(size_t)i * np + n] = (float)(fs[(size_t)i * np + n] - kWh[i] * rref[n]);
+            for (size_t n = 0; n < np; ++n)
+                dev[(size_t)i * np + n] = (float)(fs[(size_t)i * np + n] - kWh[i] * (double)r32[n]);
         for (int i = 0; i < 9; ++i)
             PB_HIP(hipMemcpy2DAsync((float *)d->hd.f[par] + (size_t)i * nyf * d->pitch, (size_t)d->pitch * 4,
                                     dev.data() + (size_t)i * np, (size_t)nx * 4, (size_t)nx * 4, nyf,
                                     hipMemcpyHostToDevice, d->stream));
+        PB_HIP(hipMemcpy2DAsync(d->hd.rho[par], (size_t)d->pitch * 4, r32.data(), (size_t)nx * 4, (size_t)nx * 4, nyf,
+                                hipMemcpyHostToDevice, d->stream));
         PB_HIP(hipStreamSynchronize(d->stream));
     }
-    if ((rc = copy_rows_h2d(d, d->hd.rho[par], rref.data(), nyf))) return rc;
     for (int b = 0; b < 2; ++b)
         if ((rc = copy_rows_h2d(d, d->hd.T[b], T, d->nr))) return rc;
     PB_HIP(hipMemsetAsync(d->hd.err, 0, sizeof(int32_t), d->stream));
@@ -658,7 +665,7 @@ int pb_profile_steps(pb_domain *d, int64_t n, double *avg_ms) {
         const int64_t tk = d->t + k + 1;
         if (err == hipSuccess && sampling && tk >= d->hd.fl_ta && tk < d->hd.fl_tb &&
             (tk - d->hd.fl_ta) % d->hd.fl_every == 0)
-            err = pb_launch_flux(dp, 1, k, d->stream);
+            err = pb_launch_flux(d->cfg.precision, dp, 1, k, d->stream);
     }
     if (err == hipSuccess) err = hipEventRecord(ev[2 * m], d->stream);
     if (err == hipSuccess) err = pb_launch_advance(d->dptr, 1, m, d->stream);
@@ -798,7 +805,7 @@ static int batch_enqueue(pb_batch *b, int nsteps, const std::vector<char> &flux)
                                   b->stream));
         if (b->nt_th > 0)
             PB_HIP(pb_launch_thermal(b->prec, b->tvar, dp, b->dtiles_th, b->nt_th, b->grid_th, k, b->stream));
-        if (flux[k]) PB_HIP(pb_launch_flux(dp, nd, k, b->stream));
+        if (flux[k]) PB_HIP(pb_launch_flux(b->prec, dp, nd, k, b->stream));
     }
     PB_HIP(pb_launch_advance(b->dptrs, nd, nsteps, b->stream));
     return PB_OK;

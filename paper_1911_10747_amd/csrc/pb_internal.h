@@ -20,7 +20,7 @@ struct PbDesc {
     int32_t pad1;
     // state
     void *f[2];          // populations [9][nyf][pitch], double or float (deviation)
-    double *rho[2];      // rho(t) written by the flow kernel, [nyf][pitch]
+    void *rho[2];        // rho(t) written by the flow kernel, [nyf][pitch]; FP32 with FP32 storage
     void *vx, *vy;       // v(t) written by the flow kernel, [nyf][pitch]; FP32 with FP32 storage
     double *T[2];        // temperature [nr][pitch]
     // boundary data [nx]
@@ -55,9 +55,9 @@ hipError_t pb_launch_flow(int prec, int mode, int tile_variant, const PbDesc *co
                           int ntiles, int grid, int k, hipStream_t s);
 hipError_t pb_launch_thermal(int prec, int tile_variant, const PbDesc *const *d_descs, const PbTile *d_tiles,
                              int ntiles, int grid, int k, hipStream_t s);
-hipError_t pb_launch_flux(const PbDesc *const *d_descs, int ndom, int k, hipStream_t s);
+hipError_t pb_launch_flux(int prec, const PbDesc *const *d_descs, int ndom, int k, hipStream_t s);
 hipError_t pb_launch_advance(PbDesc *const *d_descs, int ndom, int nsteps, hipStream_t s);
-hipError_t pb_launch_init(int prec, const PbDesc *d_desc, int par, hipStream_t s);
+hipError_t pb_launch_init(int prec, const PbDesc *d_desc, const double *rho_src, hipStream_t s);
 
 // Tile geometry of the variants (x, y extents of one block's tile).
 void pb_flow_tile_shape(int variant, int *bx, int *by);

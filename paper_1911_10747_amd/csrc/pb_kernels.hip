@@ -20,8 +20,10 @@
 // Layout: SoA populations f[i][y][x] with x fastest and a padded row pitch; a
 // wavefront covers 64 consecutive x of one row, so every pull and store is a
 // coalesced row segment.  The flow step computes in FP64; PB_FP32_DEV stores
-// f*_i - w_i rho(x) in FP32 and rebuilds f in FP64 on load, and runs the
-// energy equation in FP32 increments over FP64 T (see the FP32 sweep below).
+// rho(x) in FP32 and f*_i - w_i rho(x) in FP32 against that stored density
+// (so the FP64 rebuild on load is exact up to the rounding of the deviation),
+// and runs the energy equation in FP32 increments over FP64 T (see the FP32
+// sweep below).
 #include <type_traits>
 
 #include "pb_internal.h"
@@ -94,10 +96,10 @@ __device__ __forceinline__ double eos_psi(cdesc &d, double rho, double T, bool &
 
 // Pull f_i(x, y, t) = f*_i(x - e_i, t-1), halfway bounce-back at the walls
 // (general path, any node).  FP32 deviation storage rebuilds
-// f* = w_i rho_ref + delta with rho_ref the density of the node the value was
-// stored at.
+// f* = w_i rho_ref + delta with rho_ref the stored (FP32) density of the node
+// the value was stored at, the same value its encoding used.
 template <typename FT>
-__device__ __forceinline__ void pull_node(cdesc &d, const FT PB_GAS *fin, const double PB_GAS *rin, int x, int y,
+__device__ __forceinline__ void pull_node(cdesc &d, const FT PB_GAS *fin, const FT PB_GAS *rin, int x, int y,
                                           bool pery, double f[9]) {
     const uint32_t plane = (uint32_t)d.nyf * (uint32_t)d.pitch;
 #pragma unroll
@@ -115,7 +117,7 @@ __device__ __forceinline__ void pull_node(cdesc &d, const FT PB_GAS *fin, const 
         const uint32_t idx = (uint32_t)ys * (uint32_t)d.pitch + (uint32_t)xs;
         const FT v = fin[(uint32_t)ii * plane + idx];
         if constexpr (std::is_same<FT, float>::value)
-            f[i] = kW[i] * rin[idx] + (double)v;
+            f[i] = kW[i] * (double)rin[idx] + (double)v;
         else
             f[i] = v;
     }
@@ -124,14 +126,14 @@ __device__ __forceinline__ void pull_node(cdesc &d, const FT PB_GAS *fin, const 
 // Same pull for a node whose nine sources are all inside the fluid and away
 // from the x edges: constant offsets, no branches.
 template <typename FT>
-__device__ __forceinline__ void pull_inner(const FT PB_GAS *fin, const double PB_GAS *rin, uint32_t plane,
+__device__ __forceinline__ void pull_inner(const FT PB_GAS *fin, const FT PB_GAS *rin, uint32_t plane,
                                            uint32_t pitch, uint32_t idx, double f[9]) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const uint32_t src = idx - (uint32_t)(kEY[i] * (int)pitch) - (uint32_t)kEX[i];
         const FT v = (fin + (uint32_t)i * plane)[src];
         if constexpr (std::is_same<FT, float>::value)
-            f[i] = kW[i] * rin[src] + (double)v;
+            f[i] = kW[i] * (double)rin[src] + (double)v;
         else
             f[i] = v;
     }
@@ -150,16 +152,17 @@ __device__ __forceinline__ void load_inner_raw(const float PB_GAS *fin, uint32_t
     }
 }
 template <int RW>
-__device__ __forceinline__ void decode_lds(const double *s_rho, int lx, int ly, const float v[9], double f[9]) {
+__device__ __forceinline__ void decode_lds(const float *s_rho, int lx, int ly, const float v[9], double f[9]) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = kW[i] * s_rho[(ly - kEY[i]) * RW + lx - kEX[i]] + (double)v[i];
+    for (int i = 0; i < 9; ++i) f[i] = kW[i] * (double)s_rho[(ly - kEY[i]) * RW + lx - kEX[i]] + (double)v[i];
 }
 
-// FP32 storage keeps f* - w_i rho(t) (the deviation), FP64 storage f* itself
+// FP32 storage keeps f* - w_i rho_ref (the deviation) with rho_ref = rho(t)
+// rounded to FP32, the density stored beside it; FP64 storage f* itself
 template <typename FT>
-__device__ __forceinline__ FT encode_pop(int i, double fs, double rho) {
+__device__ __forceinline__ FT encode_pop(int i, double fs, double rho_ref) {
     if constexpr (std::is_same<FT, float>::value)
-        return (float)(fs - kW[i] * rho);
+        return (float)(fs - kW[i] * rho_ref);
     else
         return fs;
 }
@@ -168,13 +171,13 @@ __device__ __forceinline__ FT encode_pop(int i, double fs, double rho) {
 template <typename FT>
 struct GlobalStore {
     FT PB_GAS *f;
-    double PB_GAS *rho;
+    FT PB_GAS *rho;
     FT PB_GAS *vx;
     FT PB_GAS *vy;
     uint32_t plane, oidx;
     __device__ __forceinline__ void pop(int i, FT v) const { (f + (uint32_t)i * plane)[oidx] = v; }
     __device__ __forceinline__ void fields(double r, FT ux, FT uy) const {
-        rho[oidx] = r;
+        rho[oidx] = (FT)r;
         vx[oidx] = ux;
         vy[oidx] = uy;
     }
@@ -289,16 +292,17 @@ __device__ __forceinline__ bool node_update(cdesc &d, const double f[9], const M
         const double a6 = ms6 * (1.0 / 12.0), a7 = ms7 * 0.25, a8 = ms8 * 0.25;
         const double c0 = a0 - a1 - 2.0 * a2;       // axis-common part
         const double cd = a0 + 2.0 * a1 + a2;       // diagonal-common part
-        st.pop(0, encode_pop<FT>(0, a0 - 4.0 * a1 + 4.0 * a2, rho));
-        st.pop(1, encode_pop<FT>(1, c0 + a3 - 2.0 * a4 + a7, rho));
-        st.pop(2, encode_pop<FT>(2, c0 + a5 - 2.0 * a6 - a7, rho));
-        st.pop(3, encode_pop<FT>(3, c0 - a3 + 2.0 * a4 + a7, rho));
-        st.pop(4, encode_pop<FT>(4, c0 - a5 + 2.0 * a6 - a7, rho));
-        st.pop(5, encode_pop<FT>(5, cd + a3 + a4 + a5 + a6 + a8, rho));
-        st.pop(6, encode_pop<FT>(6, cd - a3 - a4 + a5 + a6 - a8, rho));
-        st.pop(7, encode_pop<FT>(7, cd - a3 - a4 - a5 - a6 + a8, rho));
-        st.pop(8, encode_pop<FT>(8, cd + a3 + a4 - a5 - a6 - a8, rho));
-        st.fields(rho, (FT)vx, (FT)vy);      // v in FP32 with FP32 storage
+        const double rref = (double)(FT)rho;        // the density as stored
+        st.pop(0, encode_pop<FT>(0, a0 - 4.0 * a1 + 4.0 * a2, rref));
+        st.pop(1, encode_pop<FT>(1, c0 + a3 - 2.0 * a4 + a7, rref));
+        st.pop(2, encode_pop<FT>(2, c0 + a5 - 2.0 * a6 - a7, rref));
+        st.pop(3, encode_pop<FT>(3, c0 - a3 + 2.0 * a4 + a7, rref));
+        st.pop(4, encode_pop<FT>(4, c0 - a5 + 2.0 * a6 - a7, rref));
+        st.pop(5, encode_pop<FT>(5, cd + a3 + a4 + a5 + a6 + a8, rref));
+        st.pop(6, encode_pop<FT>(6, cd - a3 - a4 + a5 + a6 - a8, rref));
+        st.pop(7, encode_pop<FT>(7, cd - a3 - a4 - a5 - a6 + a8, rref));
+        st.pop(8, encode_pop<FT>(8, cd + a3 + a4 - a5 - a6 - a8, rref));
+        st.fields(rho, (FT)vx, (FT)vy);      // rho and v in FP32 with FP32 storage
     }
     return !(rho == rho) || !(vx - vx == 0.0) || !(vy - vy == 0.0);
 }
@@ -308,7 +312,7 @@ __device__ __forceinline__ bool node_update(cdesc &d, const double f[9], const M
 // velocity and collision on the tile.  INNER: every node of the tile and its
 // ring is at least two nodes from the x edges and from the walls.
 template <typename FT, int BX, int BY, int MODE, bool INNER>
-__device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, double *s_psi, double *s_rho,
+__device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, double *s_psi, FT *s_rho,
                                           int *s_bad) {
     constexpr int RW = BX + 4, RH = BY + 4;        // rho(t-1) copy: tile plus two rings
     constexpr bool RLDS = INNER && std::is_same<FT, float>::value;
@@ -318,7 +322,7 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
     const bool pery = (d.flags & F_PERY) != 0;
     const int pin = (int)((d.par0 + k) & 1), pout = pin ^ 1;
     const FT PB_GAS *fin = gcast<FT>(d.f[pin]);
-    const double PB_GAS *rin = gcast<double>(d.rho[pin]);
+    const FT PB_GAS *rin = gcast<FT>(d.rho[pin]);
     const double PB_GAS *Tt = gcast<double>(d.T[pin]);
     const uint32_t pitch = (uint32_t)d.pitch, plane = (uint32_t)d.nyf * pitch;
     const uint32_t toff = (uint32_t)d.nys * pitch;           // fluid row 0 in the T array
@@ -352,7 +356,7 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
         // nodes from every edge), then the populations and T of this thread's
         // node and of its ring node.
         constexpr int NQ = (RW * RH + BX * BY - 1) / (BX * BY);
-        double rq[NQ];
+        float rq[NQ];
 #pragma unroll
         for (int u = 0; u < NQ; ++u) {
             const int q = threadIdx.x + u * BX * BY;
@@ -437,7 +441,7 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
             }
         }
         const uint32_t oidx = (uint32_t)yr * pitch + (uint32_t)xr;
-        const GlobalStore<FT> st{gcast_w<FT>(d.f[pout]), gcast_w<double>(d.rho[pout]), gcast_w<FT>(d.vx),
+        const GlobalStore<FT> st{gcast_w<FT>(d.f[pout]), gcast_w<FT>(d.rho[pout]), gcast_w<FT>(d.vx),
                                  gcast_w<FT>(d.vy), plane, oidx};
         if (node_update<FT, MODE>(d, f, mo, psi, pn, gw, wmask, oidx, st) || bad)
             *s_bad = 1;
@@ -450,7 +454,7 @@ __global__ __launch_bounds__(BX *BY) void k_flow(const PbDesc *const *__restrict
     constexpr int LW = BX + 2, LH = BY + 2;
     static_assert(2 * LW + 2 * BY <= BX * BY, "halo larger than block");
     __shared__ double s_psi[LW * LH];
-    __shared__ double s_rho[(BX + 4) * (BY + 4)];
+    __shared__ FT s_rho[(BX + 4) * (BY + 4)];
     __shared__ int s_bad;
     for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
         const PbTile te = tiles[tl];
@@ -747,8 +751,8 @@ __device__ __forceinline__ void thermal_strip(cdesc &d, const PbTile &te, int k,
 // ------------------------------------------- energy step, FP32 arithmetic
 // The same sweep for FP32-deviation storage with the energy equation's
 // arithmetic in FP32 (the FP32 VALU issues twice as many instructions per
-// cycle as the FP64 one).  What stays FP64: T in HBM, the density and the
-// EOS-derivative coefficients A(rho), B(rho) of the latent term, the
+// cycle as the FP64 one).  What stays FP64: T in HBM, the EOS-derivative
+// coefficients A(rho), B(rho) of the latent term (from the stored FP32 rho), the
 // differences T(x + e_i) - T(x) that enter stage 1, and the final update
 // T(t+1) = T(t) + (h1 + 2 h2 + 2 h3 + h4) / 6, whose FP32 increment is added to
 // the FP64 T.  The stages are carried as increments: with the operator
@@ -769,15 +773,15 @@ struct Coef9s {
 // need no load (heater, T_top); a fluid row's comes from rho when used.
 struct RowInS {
     int kind;
-    double T0, rho;
-    float lam, vx, vy;
+    double T0;
+    float rho, lam, vx, vy;   // rho as stored: converted where used, so a prefetch does not wait on it
 };
 
 template <bool FL>
-__device__ __forceinline__ RowInS load_row_s(cdesc &d, const double PB_GAS *Tin, const double PB_GAS *rho,
+__device__ __forceinline__ RowInS load_row_s(cdesc &d, const double PB_GAS *Tin, const float PB_GAS *rho,
                                              const float PB_GAS *vxg, const float PB_GAS *vyg, int n, int xg,
                                              bool pery, float lam_s) {
-    RowInS r{KIND_NONE, 0.0, 0.0, 0.0f, 0.0f, 0.0f};
+    RowInS r{KIND_NONE, 0.0, 0.0f, 0.0f, 0.0f, 0.0f};
     if constexpr (FL) {
         const uint32_t fi = (uint32_t)(n - d.nys) * (uint32_t)d.pitch + (uint32_t)xg;
         r.T0 = Tin[(uint32_t)n * (uint32_t)d.pitch + (uint32_t)xg];
@@ -843,7 +847,7 @@ __device__ __forceinline__ void thermal_strip_sp(cdesc &d, const PbTile &te, int
     const int64_t t1 = d.t0 + k + 1;
     const double PB_GAS *Tin = gcast<double>(d.T[pin]);
     double PB_GAS *Tout = gcast_w<double>(d.T[pout]);
-    const double PB_GAS *rhog = gcast<double>(d.rho[pout]);   // rho(t) written by this step's flow
+    const float PB_GAS *rhog = gcast<float>(d.rho[pout]);     // rho(t) written by this step's flow
     const float PB_GAS *vxg = gcast<float>(d.vx);
     const float PB_GAS *vyg = gcast<float>(d.vy);
     int xg = (te.x0 - 4 + lane) % d.nx;
@@ -858,7 +862,7 @@ __device__ __forceinline__ void thermal_strip_sp(cdesc &d, const PbTile &te, int
     // carried state; "_1" = row n-1, "_2" = row n-2 and so on
     int kind_1 = KIND_NONE;
     float lam_1 = 0.0f, lamR_1 = 0.0f;
-    double rho_1 = 0.0;
+    float rho_1 = 0.0f;
     float vx_1 = 0.0f, vy_1 = 0.0f, vy_2 = 0.0f;
     float p_1 = 0.0f, m_1 = 0.0f, p_2 = 0.0f, m_2 = 0.0f;
     float lN_2 = 0.0f, lNEL_2 = 0.0f, lNWR_2 = 0.0f;
@@ -887,7 +891,7 @@ __device__ __forceinline__ void thermal_strip_sp(cdesc &d, const PbTile &te, int
         // keep the loads of row n+2 here: the scheduler would otherwise sink
         // them next to their use to save registers and lose the prefetch
         __builtin_amdgcn_sched_barrier(0);
-        if (FL || cur.kind == KIND_FLUID) cur.lam = cvchi * (float)cur.rho;
+        if (FL || cur.kind == KIND_FLUID) cur.lam = cvchi * cur.rho;
 
         const float lamL = from_left(cur.lam), lamR = from_right(cur.lam);
         const float dR = (float)(from_right(cur.T0) - cur.T0), dL = (float)(from_left(cur.T0) - cur.T0);
@@ -900,7 +904,7 @@ __device__ __forceinline__ void thermal_strip_sp(cdesc &d, const PbTile &te, int
         const bool fluid_1 = FL || kind_1 == KIND_FLUID;
         const float dE = hlink_div<FL>(lam_1, lamR_1, sE), dN = hlink_div<FL>(lam_1, cur.lam, sN);
         const float dNE = hlink_div<FL>(lam_1, lamR, sNE), dNW = hlink_div<FL>(lam_1, lamL, sNW);
-        const float dC = fluid_1 ? (float)rho_1 * cv : 1.0f;
+        const float dC = fluid_1 ? rho_1 * cv : 1.0f;
         const float p1 = dE * dN, p2 = p1 * dNE, p3 = p2 * dNW, p4 = p3 * dC;
         float rr = frcp_s(p4);
         const float iC = rr * p3;
@@ -927,11 +931,11 @@ __device__ __forceinline__ void thermal_strip_sp(cdesc &d, const PbTile &te, int
             cf.k1 = c1; cf.k2 = c2; cf.k3 = c3; cf.k4 = c4;
             cf.k5 = c5; cf.k6 = c6; cf.k7 = c7; cf.k8 = c8;
             if (fluid_1) {
-                const double br = d.b * rho_1;
+                const double r1 = rho_1, br = d.b * r1;
                 const double q1 = 1.0 - br, q2 = 1.0 + 2.0 * br - br * br;
                 const double iq = frcp(q1 * q2);
-                const float A = (float)(rho_1 * d.R * q2 * iq);                     // rho R / (1 - b rho)
-                const float B = (float)(d.a * d.kappa * rho_1 * rho_1 * q1 * iq);   // a kappa rho^2 / (1 + 2 b rho - b^2 rho^2)
+                const float A = (float)(r1 * d.R * q2 * iq);                  // rho R / (1 - b rho)
+                const float B = (float)(d.a * d.kappa * r1 * r1 * q1 * iq);   // a kappa rho^2 / (1 + 2 b rho - b^2 rho^2)
                 const float divv = 3.0f * ((UR - VL) + (1.0f / 9.0f) * (cur.vy - vy_2));
                 const float AL = -C1 * divv * A, BE = -C1 * divv * B;
                 lin = AL - BE * lat_a;
@@ -1046,6 +1050,7 @@ __global__ __launch_bounds__(64, WPE) void k_thermal_sweep(const PbDesc *const *
 // Section 4.1: the Dirichlet row directly under the fluid) Eq. 36 has no
 // heater rows to difference and the bottom flux is the link flux into the
 // fluid.
+template <typename RT>
 __global__ __launch_bounds__(256) void k_flux(const PbDesc *const *__restrict__ dps, int k) {
     cdesc &d = *(const PbDesc PB_CAS *)dps[blockIdx.x];
     const int64_t t = d.t0 + k + 1;
@@ -1053,7 +1058,7 @@ __global__ __launch_bounds__(256) void k_flux(const PbDesc *const *__restrict__ 
     if (t < d.fl_ta || t >= d.fl_tb || ((t - d.fl_ta) % d.fl_every) != 0) return;
     const int pout = (int)((d.par0 + k + 1) & 1);
     const double PB_GAS *T = gcast<double>(d.T[pout]);
-    const double PB_GAS *rho = gcast<double>(d.rho[pout]);
+    const RT PB_GAS *rho = gcast<RT>(d.rho[pout]);
     __shared__ double sb[256], st[256], sw[256];
     double ab = 0.0, at = 0.0, aw = 0.0;
     const int r = d.nys - 1;
@@ -1068,7 +1073,7 @@ __global__ __launch_bounds__(256) void k_flux(const PbDesc *const *__restrict__ 
         const double ws[3] = {1.0 / 9.0, 1.0 / 36.0, 1.0 / 36.0};
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            const double lf = d.Cvchi * rho[xs[j]];
+            const double lf = d.Cvchi * (double)rho[xs[j]];
             const double lh = 2.0 * d.lambda_S * lf / (d.lambda_S + lf);
             link += ws[j] * lh * (T[(size_t)(r + 1) * d.pitch + xs[j]] - Tr);
         }
@@ -1107,9 +1112,11 @@ __global__ __launch_bounds__(256) void k_flux(const PbDesc *const *__restrict__ 
 // post-collision values at the source node, so slot (i, y) receives the value
 // node y + e_i will pull, or, when y + e_i is a wall, the value y pulls back
 // as f_opp(i); both buffers are written so frozen-flow runs see the same
-// state on either parity.  rho is copied to both rho buffers; v = 0.
+// state on either parity.  rho (FP64, [nyf][pitch] at rsrc) is stored in both
+// rho buffers (as FP32 with FP32 storage, the reference of the deviations,
+// which are taken against that stored value); v = 0.
 template <typename FT>
-__global__ __launch_bounds__(256) void k_init(const PbDesc *__restrict__ dp, int par) {
+__global__ __launch_bounds__(256) void k_init(const PbDesc *__restrict__ dp, const double *__restrict__ rsrc) {
     const PbDesc &d = *dp;
     const bool pery = (d.flags & F_PERY) != 0;
     const size_t plane = (size_t)d.nyf * d.pitch;
@@ -1117,8 +1124,10 @@ __global__ __launch_bounds__(256) void k_init(const PbDesc *__restrict__ dp, int
     for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < nn; q += (size_t)gridDim.x * blockDim.x) {
         const int y = (int)(q / d.nx), x = (int)(q % d.nx);
         const size_t idx = (size_t)y * d.pitch + x;
-        const double r = d.rho[par][idx];
-        d.rho[par ^ 1][idx] = r;
+        const double r = rsrc[idx];
+        const FT rs = (FT)r;
+        ((FT *)d.rho[0])[idx] = rs;
+        ((FT *)d.rho[1])[idx] = rs;
         ((FT *)d.vx)[idx] = (FT)0;
         ((FT *)d.vy)[idx] = (FT)0;
 #pragma unroll
@@ -1126,12 +1135,12 @@ __global__ __launch_bounds__(256) void k_init(const PbDesc *__restrict__ dp, int
             const int xd = wrap_once(x + kEX[i], d.nx);
             int yd = y + kEY[i];
             if (pery) yd = wrap_once(yd, d.nyf);
-            const double rd = (yd >= 0 && yd < d.nyf) ? d.rho[par][(size_t)yd * d.pitch + xd] : r;
+            const double rd = (yd >= 0 && yd < d.nyf) ? rsrc[(size_t)yd * d.pitch + xd] : r;
             const double fe = kW[i] * rd;
             for (int b = 0; b < 2; ++b) {
                 FT *fo = (FT *)d.f[b];
                 if constexpr (std::is_same<FT, float>::value)
-                    fo[(size_t)i * plane + idx] = (float)(fe - kW[i] * r);
+                    fo[(size_t)i * plane + idx] = (float)(fe - kW[i] * (double)rs);
                 else
                     fo[(size_t)i * plane + idx] = fe;
             }
@@ -1222,8 +1231,11 @@ hipError_t pb_launch_thermal(int prec, int variant, const PbDesc *const *dps, co
                      : launch_thermal_t<float>(variant, dps, d_tiles, ntiles, grid, k, s);
 }
 
-hipError_t pb_launch_flux(const PbDesc *const *d_descs, int ndom, int k, hipStream_t s) {
-    hipLaunchKernelGGL(k_flux, dim3(ndom), dim3(256), 0, s, d_descs, k);
+hipError_t pb_launch_flux(int prec, const PbDesc *const *d_descs, int ndom, int k, hipStream_t s) {
+    if (prec == 0)
+        hipLaunchKernelGGL(k_flux<double>, dim3(ndom), dim3(256), 0, s, d_descs, k);
+    else
+        hipLaunchKernelGGL(k_flux<float>, dim3(ndom), dim3(256), 0, s, d_descs, k);
     return hipGetLastError();
 }
 
@@ -1232,10 +1244,10 @@ hipError_t pb_launch_advance(PbDesc *const *d_descs, int ndom, int nsteps, hipSt
     return hipGetLastError();
 }
 
-hipError_t pb_launch_init(int prec, const PbDesc *d_desc, int par, hipStream_t s) {
+hipError_t pb_launch_init(int prec, const PbDesc *d_desc, const double *rho_src, hipStream_t s) {
     if (prec == 0)
-        hipLaunchKernelGGL(k_init<double>, dim3(1024), dim3(256), 0, s, d_desc, par);
+        hipLaunchKernelGGL(k_init<double>, dim3(1024), dim3(256), 0, s, d_desc, rho_src);
     else
-        hipLaunchKernelGGL(k_init<float>, dim3(1024), dim3(256), 0, s, d_desc, par);
+        hipLaunchKernelGGL(k_init<float>, dim3(1024), dim3(256), 0, s, d_desc, rho_src);
     return hipGetLastError();
 }
