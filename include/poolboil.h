@@ -89,7 +89,7 @@ typedef struct pb_config {
                                      /* 128x4, 32x16 or 64x16 nodes; 0,0 = 64x8;  */
                                      /* every tile gives the same bits           */
     int32_t thermal_tile;            /* energy-equation strips of 56 columns by */
-                                     /* 28, 20, 24, 16, 12 or 8 rows (1..6);     */
+                                     /* 28, 20, 24, 16, 12, 8 or 36 rows (1..7); */
                                      /* 0 = chosen from the domain size (tall    */
                                      /* strips for large domains, short ones for */
                                      /* small); every variant gives the same bits */
@@ -137,7 +137,8 @@ int pb_domain_bytes(const pb_config *cfg, size_t *bytes);
 /* Rows of the energy-equation strips (56 columns wide, Eqs. 24-28 swept upwards
  * by one wavefront each) a domain with this configuration uses: the explicit
  * thermal_tile, or for thermal_tile = 0 the tallest strips that still give
- * about 3072 strips (one per SIMD slot), else the shortest.  Host only;
+ * about 3072 strips (one per SIMD slot; at most 28 rows for PB_FP64), else
+ * the shortest.  Host only;
  * PB_EINVAL for an invalid configuration. */
 int pb_thermal_strip_rows(const pb_config *cfg, int *rows);
 

@@ -15,7 +15,7 @@ from . import poolboil as pb
 from . import presets
 
 FLOW_TILES = [(64, 4), (64, 8), (32, 8), (128, 4), (32, 16), (64, 16)]
-THERMAL_VARIANTS = list(range(1, 7))   # config values: strips of 28, 20, 24, 16, 12, 8 rows (0 = by size)
+THERMAL_VARIANTS = list(range(1, 8))   # config values: strips of 28, 20, 24, 16, 12, 8, 36 rows (0 = by size)
 CACHE = os.environ.get("POOLBOIL_TUNE_CACHE", os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                             "tune_cache.json"))
 

@@ -67,6 +67,9 @@ int thermal_variant_of(const pb_config &c) {
     for (int v = 0; v < pb_thermal_variants(); ++v) {
         int bx, by;
         pb_thermal_tile_shape(v, &bx, &by);
+        // FP64 strips stop at 28 rows: its sweep measured slower with 36
+        // (4096 x 2112: 132 us against 127.5; FP32: 76.3 against 79.7)
+        if (c.precision == PB_FP64 && by > 28) continue;
         if (ntiles_for(c.nx, nr, bx, by) >= 3072 && by > best_h) {
             best = v;
             best_h = by;
@@ -171,15 +174,15 @@ void make_tiles(std::vector<PbTile> &out, int dom, int nx, int ny, int bx, int b
 
 // Energy-strip work-list of one domain (slots: wavefronts the chip holds at
 // once, 256 CUs x 4 SIMDs x the sweep's waves per SIMD).  Strips of by rows;
-// when there are more than one and a half slots' worth of them, the top rows
-// become 8-row strips (short_strip = 1) about 0.6 slots in number, placed last: the
-// wavefronts that start last are then short and the launch ends with few idle
-// slots (4096 x 2112 rows, FP32: 91.5 -> 81.7 us).  Each part is ordered for
-// the XCDs on its own.
+// when there are more of them than slots, the top rows become 8-row strips
+// (short_strip = 1) about 0.6 slots in number, placed last: the wavefronts
+// that start last are then short and the launch ends with few idle slots
+// (4096 x 2112 rows, FP32, 28-row strips: 91.5 -> 81.7 us).  Each part is
+// ordered for the XCDs on its own.
 void make_thermal_tiles(std::vector<PbTile> &out, int dom, int nx, int nr, int bx, int by, int slots) {
     const int cols = (nx + bx - 1) / bx;
     int ytail = nr;
-    if (by > 8 && (int64_t)cols * ((nr + by - 1) / by) * 2 > 3 * (int64_t)slots) {
+    if (by > 8 && (int64_t)cols * ((nr + by - 1) / by) > (int64_t)slots) {
         const int trows = 8 * std::max(1, (int)(0.6 * slots / cols + 0.5));
         ytail = std::max(0, (nr - trows) / by * by);
     }

@@ -1167,7 +1167,7 @@ __global__ void k_advance(PbDesc *const *__restrict__ dps, int ndom, int nsteps)
 static const int kFlowShapes[][2] = {{64, 4}, {64, 8}, {32, 8}, {128, 4}, {32, 16}, {64, 16}};
 // column sweeps of 56 written columns x H rows
 // the whole strip is unrolled so the operator ring lives in registers
-static const int kThermalShapes[][2] = {{56, 28}, {56, 20}, {56, 24}, {56, 16}, {56, 12}, {56, 8}};
+static const int kThermalShapes[][2] = {{56, 28}, {56, 20}, {56, 24}, {56, 16}, {56, 12}, {56, 8}, {56, 36}};
 
 int pb_flow_variants() { return (int)(sizeof(kFlowShapes) / sizeof(kFlowShapes[0])); }
 int pb_thermal_variants() { return (int)(sizeof(kThermalShapes) / sizeof(kThermalShapes[0])); }
@@ -1220,6 +1220,7 @@ static hipError_t launch_thermal_t(int variant, const PbDesc *const *dps, const 
         case 3: hipLaunchKernelGGL((k_thermal_sweep<VT, 16, 2, 24>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
         case 4: hipLaunchKernelGGL((k_thermal_sweep<VT, 12, 2, 20>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
         case 5: hipLaunchKernelGGL((k_thermal_sweep<VT, 8, 2, 16>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
+        case 6: hipLaunchKernelGGL((k_thermal_sweep<VT, 36, 2, 44>), dim3(grid), dim3(64), 0, s, dps, d_tiles, ntiles, k); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

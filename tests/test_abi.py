@@ -73,17 +73,19 @@ def test_invalid_configs_rejected_without_gpu():
 
 
 def test_energy_strip_height_by_domain_size():
-    """thermal_tile 0 picks the energy strips from the domain size: 28-row
-    strips where there are enough of them to give every SIMD slot one (the
-    4096x2048 + 4096x64 roofline domain: 74 x 76 = 5624), 8-row strips for a
-    small domain (400x400 + 400x20: 8 x 53 = 424 strips), and 1..6 select
-    28, 20, 24, 16, 12 or 8 rows explicitly.  Host only."""
+    """thermal_tile 0 picks the energy strips from the domain size: the
+    tallest strips of which there are enough to give every SIMD slot one (the
+    4096x2048 + 4096x64 roofline domain: 74 x 59 = 4366 strips of 36 rows with
+    FP32-deviation storage; FP64 strips stop at 28 rows, 74 x 76 = 5624),
+    8-row strips for a small domain (400x400 + 400x20: 8 x 53 = 424 strips),
+    and 1..7 select 28, 20, 24, 16, 12, 8 or 36 rows explicitly.  Host only."""
     from paper_1911_10747_amd import poolboil as pb
     P = dict(W.BASE_PARAMS, Tc=0.07, rho_L=6.5, rho_V=0.38, rho_S=19.5)
     rows = lambda **kw: pb.thermal_strip_rows(pb.make_config(**dict(P, **kw)))
-    assert rows(nx=4096, ny_fluid=2048, ny_solid=64) == 28
+    assert rows(nx=4096, ny_fluid=2048, ny_solid=64, precision=1) == 36
+    assert rows(nx=4096, ny_fluid=2048, ny_solid=64, precision=0) == 28
     assert rows(nx=400, ny_fluid=400, ny_solid=20) == 8
     assert rows(nx=2048, ny_fluid=1024, ny_solid=51) == 12    # 37 x 90 = 3330 strips of 12 rows
-    assert [rows(nx=400, ny_fluid=400, ny_solid=20, thermal_tile=v) for v in range(1, 7)] == [28, 20, 24, 16, 12, 8]
+    assert [rows(nx=400, ny_fluid=400, ny_solid=20, thermal_tile=v) for v in range(1, 8)] == [28, 20, 24, 16, 12, 8, 36]
     with pytest.raises(pb.PbError):
-        rows(nx=400, ny_fluid=400, ny_solid=20, thermal_tile=7)
+        rows(nx=400, ny_fluid=400, ny_solid=20, thermal_tile=8)

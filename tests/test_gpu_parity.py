@@ -45,12 +45,12 @@ def test_ragged_domain_and_tile_shapes_are_bit_identical(precision):
     """77x45 fluid over 5 heater rows (ragged against every tile shape): the
     result matches the oracle and is bit-identical for every flow tile and
     every thermal variant (strip heights 8, 12, 16 and 20 have strips inside
-    the fluid, which take the specialised path; 24 and 28 have none)."""
+    the fluid, which take the specialised path; 24, 28 and 36 have none)."""
     P, d, bc, rho, T = pool_case(77, 45, 5, superheat=0.2, n_spots=3, seed=7, y0=17)
     ref = None
     shapes = [(64, 4), (64, 8), (32, 8), (128, 4), (32, 16), (64, 16), (64, 4)]
     for i, tile in enumerate(shapes):
-        g = gpu_domain(P, bc, rho, T, precision, tile=tile, thermal_tile=1 + i % 6)
+        g = gpu_domain(P, bc, rho, T, precision, tile=tile, thermal_tile=1 + i)
         g.step(120)
         g.sync()
         r = g.read()
@@ -69,23 +69,25 @@ def test_ragged_domain_and_tile_shapes_are_bit_identical(precision):
 
 @pytest.mark.parametrize("precision,nx,nyf,nys", [(0, 3590, 1403, 56), (1, 4096, 1800, 64)])
 def test_short_tail_strips_bit_identical(precision, nx, nyf, nys):
-    """Domains with enough 28-row energy strips that the library ends the work
-    list with 8-row strips (more than 1.5x the 2048 / 3072 wavefront slots of
-    the FP64 / FP32 sweep; ragged columns and a ragged top strip): 20 steps
+    """Domains with enough 28- or 36-row energy strips that the library ends
+    the work list with 8-row strips (more than the 2048 / 3072 wavefront slots
+    of the FP64 / FP32 sweep; ragged columns and a ragged top strip): 20 steps
     give the same bits as strips of 8 rows throughout (thermal_tile 6), which
     the ragged-domain test holds to the oracle."""
     from paper_1911_10747_amd import poolboil as pb
     P, d, bc, rho, T = pool_case(nx, nyf, nys, superheat=0.15, n_spots=nx // 64, seed=3, y0=int(0.4 * nyf))
     assert pb.thermal_strip_rows(pb_config(P, precision, (64, 8), 1)) == 28
+    assert pb.thermal_strip_rows(pb_config(P, precision, (64, 8), 7)) == 36
     out = []
-    for tt in (1, 6):
+    for tt in (6, 1, 7):
         g = gpu_domain(P, bc, rho, T, precision, tile=(64, 8), thermal_tile=tt)
         g.step(20)
         g.sync()
         out.append(g.read(with_f=False))
         g.close()
     for k in ("rho", "ux", "uy", "T"):
-        np.testing.assert_array_equal(out[0][k], out[1][k], err_msg=f"{k} differs")
+        for j, tt in ((1, 1), (2, 7)):
+            np.testing.assert_array_equal(out[j][k], out[0][k], err_msg=f"{k} differs for thermal_tile {tt}")
 
 
 @pytest.mark.parametrize("tile,isothermal,precision", [((0, 0), 1, 0), ((32, 16), 1, 0), ((0, 0), 0, 0),
