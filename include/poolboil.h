@@ -194,8 +194,11 @@ double pb_rho_bar(const pb_domain *dom);          /* rho_bar of Eq. 15      */
  * the batch's own if it is NULL, each pb_batch_step ordered after the work
  * already queued on the domains' streams and before work queued there later.
  * Per-node arithmetic does not depend on the batch, so each domain's result is
- * bit-identical to stepping it alone.  persistent_blocks > 0 caps the grid
- * (blocks then loop over the work-list).  The domains must outlive the batch. */
+ * bit-identical to stepping it alone.  Tile shapes come from the first
+ * domain's configuration; when every domain has thermal_tile = 0 the energy
+ * strips are chosen for the batch's total size (pb_thermal_strip_rows's rule
+ * over all members).  persistent_blocks > 0 caps the grid (blocks then loop
+ * over the work-list).  The domains must outlive the batch. */
 int pb_batch_create(pb_domain *const *doms, int32_t n, int32_t steps_per_graph, int32_t persistent_blocks,
                     void *stream, pb_batch **out);
 int pb_batch_step(pb_batch *batch, int64_t n);

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/poolboil.h"
@@ -55,22 +56,21 @@ int flow_variant_of(const pb_config &c) {
 
 int ntiles_for(int nx, int ny, int bx, int by) { return ((nx + bx - 1) / bx) * ((ny + by - 1) / by); }
 
-// Thermal strip variant of a config: thermal_tile k >= 1 is variant k - 1;
-// 0 lets the library choose from the domain size: the tallest strips that
-// still give about one strip per SIMD slot (3072 at 3 waves per SIMD on 256
-// CUs), else the shortest, since a small domain's step time is the sweep of
-// one strip.
-int thermal_variant_of(const pb_config &c) {
-    if (c.thermal_tile > 0) return c.thermal_tile - 1;
-    const int nr = c.ny_fluid + c.ny_solid;
+// Thermal strip variant chosen from the sizes (nx, rows) of the domains one
+// launch steps: the tallest strips whose count over those domains still gives
+// about one strip per SIMD slot (3072 at 3 waves per SIMD on 256 CUs), else
+// the shortest, since a small domain's step time is the sweep of one strip.
+int thermal_variant_for(int precision, const std::vector<std::pair<int, int>> &doms) {
     int best = -1, best_h = 0, shortest = 0, shortest_h = 1 << 30;
     for (int v = 0; v < pb_thermal_variants(); ++v) {
         int bx, by;
         pb_thermal_tile_shape(v, &bx, &by);
         // FP64 strips stop at 28 rows: its sweep measured slower with 36
         // (4096 x 2112: 132 us against 127.5; FP32: 76.3 against 79.7)
-        if (c.precision == PB_FP64 && by > 28) continue;
-        if (ntiles_for(c.nx, nr, bx, by) >= 3072 && by > best_h) {
+        if (precision == PB_FP64 && by > 28) continue;
+        int64_t strips = 0;
+        for (const auto &d : doms) strips += ntiles_for(d.first, d.second, bx, by);
+        if (strips >= 3072 && by > best_h) {
             best = v;
             best_h = by;
         }
@@ -80,6 +80,13 @@ int thermal_variant_of(const pb_config &c) {
         }
     }
     return best >= 0 ? best : shortest;
+}
+
+// Thermal strip variant of a config: thermal_tile k >= 1 is variant k - 1,
+// 0 the choice above for the domain alone.
+int thermal_variant_of(const pb_config &c) {
+    if (c.thermal_tile > 0) return c.thermal_tile - 1;
+    return thermal_variant_for(c.precision, {{c.nx, c.ny_fluid + c.ny_solid}});
 }
 
 int max_tiles(int nx, int ny, bool flow) {
@@ -172,29 +179,49 @@ void make_tiles(std::vector<PbTile> &out, int dom, int nx, int ny, int bx, int b
         for (int x0 = 0; x0 < nx; x0 += bx) out.push_back(PbTile{dom, x0, y0, 0});
 }
 
-// Energy-strip work-list of one domain (slots: wavefronts the chip holds at
-// once, 256 CUs x 4 SIMDs x the sweep's waves per SIMD).  Strips of by rows;
-// when there are more of them than slots, the top rows become 8-row strips
-// (short_strip = 1) about 0.6 slots in number, placed last: the wavefronts
-// that start last are then short and the launch ends with few idle slots
-// (4096 x 2112 rows, FP32, 28-row strips: 91.5 -> 81.7 us).  Each part is
-// ordered for the XCDs on its own.
-void make_thermal_tiles(std::vector<PbTile> &out, int dom, int nx, int nr, int bx, int by, int slots) {
-    const int cols = (nx + bx - 1) / bx;
-    int ytail = nr;
-    if (by > 8 && (int64_t)cols * ((nr + by - 1) / by) > (int64_t)slots) {
-        const int trows = 8 * std::max(1, (int)(0.6 * slots / cols + 0.5));
-        ytail = std::max(0, (nr - trows) / by * by);
+// A domain's share of an energy-strip work list: index, columns, thermal rows.
+struct ThermalDom {
+    int dom, nx, nr;
+};
+
+// Energy-strip work list of one or more domains (slots: wavefronts the chip
+// holds at once, 256 CUs x 4 SIMDs x the sweep's waves per SIMD).  Strips of
+// by rows; when there are more of them than slots, the top rows of every
+// domain become 8-row strips (short_strip = 1), about 0.6 slots in all,
+// shared out by area, and are placed last: the wavefronts that start last are
+// then short and the launch ends with few idle slots (4096 x 2112 rows, FP32,
+// 28-row strips: 91.5 -> 81.7 us).  With ordered set, each part is ordered for
+// the XCDs on its own.
+void make_thermal_tiles(std::vector<PbTile> &out, const std::vector<ThermalDom> &doms, int bx, int by, int slots,
+                        bool ordered) {
+    int64_t tall = 0, area = 0;
+    for (const ThermalDom &t : doms) {
+        const int64_t cols = (t.nx + bx - 1) / bx;
+        tall += cols * ((t.nr + by - 1) / by);
+        area += cols * t.nr;
     }
+    const bool tail = by > 8 && tall > slots;
     std::vector<PbTile> big, small;
-    make_tiles(big, dom, nx, ytail, bx, by);
-    for (int y0 = ytail; y0 < nr; y0 += 8)
-        for (int x0 = 0; x0 < nx; x0 += bx) small.push_back(PbTile{dom, x0, y0, 1});
-    xcd_order(big);
-    xcd_order(small);
+    for (const ThermalDom &t : doms) {
+        int ytail = t.nr;
+        if (tail) {
+            const int trows = 8 * std::max(1, (int)(0.6 * slots * t.nr / (double)area + 0.5));
+            ytail = std::max(0, (t.nr - trows) / by * by);
+        }
+        make_tiles(big, t.dom, t.nx, ytail, bx, by);
+        for (int y0 = ytail; y0 < t.nr; y0 += 8)
+            for (int x0 = 0; x0 < t.nx; x0 += bx) small.push_back(PbTile{t.dom, x0, y0, 1});
+    }
+    if (ordered) {
+        xcd_order(big);
+        xcd_order(small);
+    }
     out.insert(out.end(), big.begin(), big.end());
     out.insert(out.end(), small.begin(), small.end());
 }
+
+// wavefront slots of the energy sweep: 3 waves per SIMD in FP32, 2 in FP64
+int thermal_slots(int precision) { return 256 * 4 * (precision == PB_FP32_DEV ? 3 : 2); }
 
 }  // namespace
 
@@ -250,7 +277,7 @@ int upload_tiles(pb_domain *d) {
     pb_flow_tile_shape(d->fvar, &bx, &by);
     make_tiles(tf, 0, d->cfg.nx, d->cfg.ny_fluid, bx, by);
     pb_thermal_tile_shape(d->tvar, &bx, &by);
-    make_thermal_tiles(tt, 0, d->cfg.nx, d->nr, bx, by, d->cfg.precision == PB_FP32_DEV ? 3072 : 2048);
+    make_thermal_tiles(tt, {ThermalDom{0, d->cfg.nx, d->nr}}, bx, by, thermal_slots(d->cfg.precision), true);
     xcd_order(tf);
     if ((int)tf.size() > max_tiles(d->cfg.nx, d->cfg.ny_fluid, true) || (int)tt.size() > max_tiles(d->cfg.nx, d->nr, false))
         return fail(PB_EINVAL, "work list longer than its table");
@@ -723,6 +750,15 @@ int pb_batch_create(pb_domain *const *doms, int32_t n, int32_t steps_per_graph, 
     b->prec = prec;
     b->fvar = doms[0]->fvar;
     b->tvar = doms[0]->tvar;
+    // members that all leave the strips to the library get strips chosen for
+    // the batch as a whole (the strips of all members fill the chip together)
+    bool auto_strips = true;
+    std::vector<std::pair<int, int>> sizes;
+    for (int j = 0; j < n; ++j) {
+        auto_strips = auto_strips && doms[j]->cfg.thermal_tile == 0;
+        if (!(doms[j]->cfg.flags & PB_ISOTHERMAL)) sizes.push_back({doms[j]->cfg.nx, doms[j]->nr});
+    }
+    if (auto_strips && !sizes.empty()) b->tvar = thermal_variant_for(prec, sizes);
     b->spg = steps_per_graph;
     std::vector<PbTile> tf, tt;
     std::vector<PbDesc *> ptrs(n);
@@ -732,19 +768,18 @@ int pb_batch_create(pb_domain *const *doms, int32_t n, int32_t steps_per_graph, 
     // a launch's work-list holds the tiles of the domains that take that part
     // of the step (frozen-flow domains skip the flow, isothermal ones the
     // energy equation, as when stepped alone)
+    std::vector<ThermalDom> tdoms;
     for (int j = 0; j < n; ++j) {
         if (!(doms[j]->cfg.flags & PB_FROZEN_FLOW)) make_tiles(tf, j, doms[j]->cfg.nx, doms[j]->cfg.ny_fluid, fbx, fby);
-        if (!(doms[j]->cfg.flags & PB_ISOTHERMAL)) make_tiles(tt, j, doms[j]->cfg.nx, doms[j]->nr, tbx, tby);
+        if (!(doms[j]->cfg.flags & PB_ISOTHERMAL)) tdoms.push_back(ThermalDom{j, doms[j]->cfg.nx, doms[j]->nr});
         ptrs[j] = doms[j]->ddesc;
     }
+    make_thermal_tiles(tt, tdoms, tbx, tby, thermal_slots(prec), persistent_blocks == 0);
     b->nt_flow = (int)tf.size();
     b->nt_th = (int)tt.size();
     b->grid_flow = persistent_blocks > 0 ? std::min(b->nt_flow, (int)persistent_blocks) : b->nt_flow;
     b->grid_th = persistent_blocks > 0 ? std::min(b->nt_th, (int)persistent_blocks) : b->nt_th;
-    if (persistent_blocks == 0) {
-        xcd_order(tf);
-        xcd_order(tt);
-    }
+    if (persistent_blocks == 0) xcd_order(tf);
     auto bad = [&](int code) {
         if (b->ev_batch) (void)hipEventDestroy(b->ev_batch);
         if (b->ev_dom) (void)hipEventDestroy(b->ev_dom);

@@ -1050,8 +1050,9 @@ __global__ __launch_bounds__(64, WPE) void k_thermal_sweep(const PbDesc *const *
 // Section 4.1: the Dirichlet row directly under the fluid) Eq. 36 has no
 // heater rows to difference and the bottom flux is the link flux into the
 // fluid.
+constexpr int kFluxThreads = 1024;   // one block per domain; few columns per thread keep it short
 template <typename RT>
-__global__ __launch_bounds__(256) void k_flux(const PbDesc *const *__restrict__ dps, int k) {
+__global__ __launch_bounds__(kFluxThreads) void k_flux(const PbDesc *const *__restrict__ dps, int k) {
     cdesc &d = *(const PbDesc PB_CAS *)dps[blockIdx.x];
     const int64_t t = d.t0 + k + 1;
     if ((d.flags & F_PERY) || d.nys < 1 || d.nyf < 1) return;
@@ -1059,10 +1060,10 @@ __global__ __launch_bounds__(256) void k_flux(const PbDesc *const *__restrict__ 
     const int pout = (int)((d.par0 + k + 1) & 1);
     const double PB_GAS *T = gcast<double>(d.T[pout]);
     const RT PB_GAS *rho = gcast<RT>(d.rho[pout]);
-    __shared__ double sb[256], st[256], sw[256];
+    __shared__ double sb[kFluxThreads], st[kFluxThreads], sw[kFluxThreads];
     double ab = 0.0, at = 0.0, aw = 0.0;
     const int r = d.nys - 1;
-    for (int x = threadIdx.x; x < d.nx; x += 256) {
+    for (int x = threadIdx.x; x < d.nx; x += kFluxThreads) {
         if (d.nys >= 3) {
             const double T0 = T[x], T1 = T[d.pitch + x], T2 = T[2 * (size_t)d.pitch + x];
             ab += -d.lambda_S * ((4.0 * T1 - T2 - 3.0 * T0) * 0.5);       // Eq. 36
@@ -1084,7 +1085,7 @@ __global__ __launch_bounds__(256) void k_flux(const PbDesc *const *__restrict__ 
     st[threadIdx.x] = at;
     sw[threadIdx.x] = aw;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
+    for (int s = kFluxThreads / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) {
             sb[threadIdx.x] += sb[threadIdx.x + s];
             st[threadIdx.x] += st[threadIdx.x + s];
@@ -1234,9 +1235,9 @@ hipError_t pb_launch_thermal(int prec, int variant, const PbDesc *const *dps, co
 
 hipError_t pb_launch_flux(int prec, const PbDesc *const *d_descs, int ndom, int k, hipStream_t s) {
     if (prec == 0)
-        hipLaunchKernelGGL(k_flux<double>, dim3(ndom), dim3(256), 0, s, d_descs, k);
+        hipLaunchKernelGGL(k_flux<double>, dim3(ndom), dim3(kFluxThreads), 0, s, d_descs, k);
     else
-        hipLaunchKernelGGL(k_flux<float>, dim3(ndom), dim3(256), 0, s, d_descs, k);
+        hipLaunchKernelGGL(k_flux<float>, dim3(ndom), dim3(kFluxThreads), 0, s, d_descs, k);
     return hipGetLastError();
 }
 

@@ -264,6 +264,35 @@ def test_batch_matches_alone_bit_exact(precision):
         g.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_of_auto_strip_domains_matches_alone(precision):
+    """Six 1000x480 + 1000x24 domains that leave the energy strips to the
+    library: alone each takes 8-row strips (18 x 63 strips), together the
+    batch takes 16-row strips (3456 of them) and ends its work list with
+    8-row strips (more strips than wavefront slots).  30 steps, bit for bit."""
+    from paper_1911_10747_amd import poolboil as pb
+    cases = [pool_case(1000, 480, 24, superheat=0.05 + 0.04 * i, n_spots=8, seed=20 + i, y0=190) for i in range(6)]
+    assert pb.thermal_strip_rows(pb_config(cases[0][0], precision)) == 8
+    alone = []
+    for P, d, bc, rho, T in cases:
+        g = gpu_domain(P, bc, rho, T, precision)
+        g.step(30)
+        g.sync()
+        alone.append(g.read(with_f=False))
+        g.close()
+    doms = [gpu_domain(P, bc, rho, T, precision) for P, d, bc, rho, T in cases]
+    batch = pb.Batch(doms, steps_per_graph=10)
+    batch.step(30)
+    for g, r0 in zip(doms, alone):
+        g.sync()
+        r = g.read(with_f=False)
+        for k in ("rho", "ux", "uy", "T"):
+            np.testing.assert_array_equal(r[k], r0[k], err_msg=k)
+    batch.close()
+    for g in doms:
+        g.close()
+
+
 def test_batch_flux_windows_set_between_graph_replays():
     """Heat-flux windows opened on batch members after the batch has captured
     and replayed its step graph, with sampling periods that do (5) and do not
