@@ -142,6 +142,20 @@ int pb_domain_bytes(const pb_config *cfg, size_t *bytes);
  * PB_EINVAL for an invalid configuration. */
 int pb_thermal_strip_rows(const pb_config *cfg, int *rows);
 
+/* The energy launch's work list for n domains stepped together (n = 1: one
+ * domain stepped alone by pb_step; n > 1: the batch pb_batch_create makes of
+ * them, without persistent_blocks), in launch order, as (domain index, x0,
+ * y0, rows) quadruples in out[4 * i .. 4 * i + 3]: a strip covers columns
+ * x0 .. x0 + 55 and thermal rows y0 .. y0 + rows - 1 (clipped to the domain).
+ * Strip height as pb_thermal_strip_rows gives for one domain (for several:
+ * the first configuration's, or, when all have thermal_tile = 0, chosen for
+ * their total size); when the strips outnumber the wavefront slots of the
+ * chip, the top rows of each domain come as 8-row strips at the end of the
+ * list.  Isothermal domains are left out.  *count receives the number of
+ * strips; out may be NULL to query it, else cap (quadruples) must hold them
+ * (PB_EINVAL otherwise).  Host only: for tests and tools. */
+int pb_thermal_work_list(const pb_config *const *cfgs, int32_t n, int32_t *out, int64_t cap, int64_t *count);
+
 /* Create a domain.  stream: a hipStream_t (NULL = the null stream).  dev_mem:
  * NULL to let the library allocate, or caller-owned device memory of at least
  * pb_domain_bytes() bytes (256-byte aligned) that must outlive the domain.

@@ -223,6 +223,31 @@ void make_thermal_tiles(std::vector<PbTile> &out, const std::vector<ThermalDom> 
 // wavefront slots of the energy sweep: 3 waves per SIMD in FP32, 2 in FP64
 int thermal_slots(int precision) { return 256 * 4 * (precision == PB_FP32_DEV ? 3 : 2); }
 
+// Strip variant of one energy launch over these domains: the first one's,
+// unless all leave the strips to the library (thermal_tile = 0); then strips
+// chosen for all of them together (for one domain, its own size).
+int launch_thermal_variant(const std::vector<const pb_config *> &cfgs) {
+    bool auto_strips = true;
+    std::vector<std::pair<int, int>> sizes;
+    for (const pb_config *c : cfgs) {
+        auto_strips = auto_strips && c->thermal_tile == 0;
+        if (!(c->flags & PB_ISOTHERMAL)) sizes.push_back({c->nx, c->ny_fluid + c->ny_solid});
+    }
+    if (auto_strips && !sizes.empty()) return thermal_variant_for(cfgs[0]->precision, sizes);
+    return thermal_variant_of(*cfgs[0]);
+}
+
+// Work list of one energy launch over these domains (isothermal ones left out)
+void thermal_list(std::vector<PbTile> &tt, const std::vector<const pb_config *> &cfgs, int tvar, bool ordered) {
+    int bx, by;
+    pb_thermal_tile_shape(tvar, &bx, &by);
+    std::vector<ThermalDom> tdoms;
+    for (int j = 0; j < (int)cfgs.size(); ++j)
+        if (!(cfgs[j]->flags & PB_ISOTHERMAL))
+            tdoms.push_back(ThermalDom{j, cfgs[j]->nx, cfgs[j]->ny_fluid + cfgs[j]->ny_solid});
+    make_thermal_tiles(tt, tdoms, bx, by, thermal_slots(cfgs[0]->precision), ordered);
+}
+
 }  // namespace
 
 struct pb_domain {
@@ -276,8 +301,7 @@ int upload_tiles(pb_domain *d) {
     std::vector<PbTile> tf, tt;
     pb_flow_tile_shape(d->fvar, &bx, &by);
     make_tiles(tf, 0, d->cfg.nx, d->cfg.ny_fluid, bx, by);
-    pb_thermal_tile_shape(d->tvar, &bx, &by);
-    make_thermal_tiles(tt, {ThermalDom{0, d->cfg.nx, d->nr}}, bx, by, thermal_slots(d->cfg.precision), true);
+    thermal_list(tt, {&d->cfg}, d->tvar, true);
     xcd_order(tf);
     if ((int)tf.size() > max_tiles(d->cfg.nx, d->cfg.ny_fluid, true) || (int)tt.size() > max_tiles(d->cfg.nx, d->nr, false))
         return fail(PB_EINVAL, "work list longer than its table");
@@ -351,6 +375,34 @@ int pb_thermal_strip_rows(const pb_config *cfg, int *rows) {
     int bx, by;
     pb_thermal_tile_shape(thermal_variant_of(*cfg), &bx, &by);
     *rows = by;
+    return PB_OK;
+}
+
+int pb_thermal_work_list(const pb_config *const *cfgs, int32_t n, int32_t *out, int64_t cap, int64_t *count) {
+    if (!cfgs || n < 1) return fail(PB_EINVAL, "need at least one configuration");
+    if (!count) return fail(PB_EINVAL, "count is NULL");
+    std::vector<const pb_config *> v(n);
+    for (int j = 0; j < n; ++j) {
+        int rc = validate(cfgs[j]);
+        if (rc) return rc;
+        if (cfgs[j]->precision != cfgs[0]->precision) return fail(PB_EINVAL, "mixed precisions in one launch");
+        v[j] = cfgs[j];
+    }
+    const int tvar = launch_thermal_variant(v);
+    int bx, by;
+    pb_thermal_tile_shape(tvar, &bx, &by);
+    std::vector<PbTile> tt;
+    thermal_list(tt, v, tvar, true);
+    *count = (int64_t)tt.size();
+    if (out && cap < (int64_t)tt.size()) return fail(PB_EINVAL, "out holds %lld strips, %lld needed", (long long)cap,
+                                                     (long long)tt.size());
+    if (out)
+        for (size_t i = 0; i < tt.size(); ++i) {
+            out[4 * i] = tt[i].dom;
+            out[4 * i + 1] = tt[i].x0;
+            out[4 * i + 2] = tt[i].y0;
+            out[4 * i + 3] = tt[i].short_strip ? 8 : by;
+        }
     return PB_OK;
 }
 
@@ -749,32 +801,22 @@ int pb_batch_create(pb_domain *const *doms, int32_t n, int32_t steps_per_graph, 
             b->dom_streams.push_back(doms[j]->stream);
     b->prec = prec;
     b->fvar = doms[0]->fvar;
-    b->tvar = doms[0]->tvar;
-    // members that all leave the strips to the library get strips chosen for
-    // the batch as a whole (the strips of all members fill the chip together)
-    bool auto_strips = true;
-    std::vector<std::pair<int, int>> sizes;
-    for (int j = 0; j < n; ++j) {
-        auto_strips = auto_strips && doms[j]->cfg.thermal_tile == 0;
-        if (!(doms[j]->cfg.flags & PB_ISOTHERMAL)) sizes.push_back({doms[j]->cfg.nx, doms[j]->nr});
-    }
-    if (auto_strips && !sizes.empty()) b->tvar = thermal_variant_for(prec, sizes);
+    std::vector<const pb_config *> cfgs(n);
+    for (int j = 0; j < n; ++j) cfgs[j] = &doms[j]->cfg;
+    b->tvar = launch_thermal_variant(cfgs);
     b->spg = steps_per_graph;
     std::vector<PbTile> tf, tt;
     std::vector<PbDesc *> ptrs(n);
-    int fbx, fby, tbx, tby;
+    int fbx, fby;
     pb_flow_tile_shape(b->fvar, &fbx, &fby);
-    pb_thermal_tile_shape(b->tvar, &tbx, &tby);
     // a launch's work-list holds the tiles of the domains that take that part
     // of the step (frozen-flow domains skip the flow, isothermal ones the
     // energy equation, as when stepped alone)
-    std::vector<ThermalDom> tdoms;
     for (int j = 0; j < n; ++j) {
         if (!(doms[j]->cfg.flags & PB_FROZEN_FLOW)) make_tiles(tf, j, doms[j]->cfg.nx, doms[j]->cfg.ny_fluid, fbx, fby);
-        if (!(doms[j]->cfg.flags & PB_ISOTHERMAL)) tdoms.push_back(ThermalDom{j, doms[j]->cfg.nx, doms[j]->nr});
         ptrs[j] = doms[j]->ddesc;
     }
-    make_thermal_tiles(tt, tdoms, tbx, tby, thermal_slots(prec), persistent_blocks == 0);
+    thermal_list(tt, cfgs, b->tvar, persistent_blocks == 0);
     b->nt_flow = (int)tf.size();
     b->nt_th = (int)tt.size();
     b->grid_flow = persistent_blocks > 0 ? std::min(b->nt_flow, (int)persistent_blocks) : b->nt_flow;

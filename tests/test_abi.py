@@ -3,6 +3,7 @@ that include/poolboil.h declares; host-only helpers work there."""
 import os
 import re
 
+import numpy as np
 import pytest
 
 from conftest import ROOT
@@ -89,3 +90,62 @@ def test_energy_strip_height_by_domain_size():
     assert [rows(nx=400, ny_fluid=400, ny_solid=20, thermal_tile=v) for v in range(1, 8)] == [28, 20, 24, 16, 12, 8, 36]
     with pytest.raises(pb.PbError):
         rows(nx=400, ny_fluid=400, ny_solid=20, thermal_tile=8)
+
+
+def _cover(strips, doms, ncol=56):
+    """Every (column block, thermal row) of every domain covered exactly once."""
+    for j, (nx, nr) in enumerate(doms):
+        grid = np.zeros((nr, (nx + ncol - 1) // ncol), dtype=np.int32)
+        for d, x0, y0, rows in strips:
+            if d == j:
+                assert x0 % ncol == 0 and 0 <= x0 < nx and 0 <= y0 < nr
+                grid[y0:y0 + rows, x0 // ncol] += 1
+        assert (grid == 1).all(), f"domain {j}: cover counts {np.unique(grid)}"
+
+
+def test_energy_work_list_ends_with_short_strips():
+    """The energy launch's work list (host only): it covers every thermal
+    row of every column block exactly once; on the 4096x2048 + 4096x64 domain
+    the tall strips (36 rows in FP32, 28 in FP64) outnumber the wavefront
+    slots (3072 / 2048), so the list ends with 8-row strips cut from the top
+    rows, about 0.6 slots of them; a small domain has 8-row strips only; a
+    batch of six 1000x480 + 1000x24 auto-strip domains takes 16-row strips for
+    the set (3456 > 3072) and ends with short strips from every member; an
+    isothermal member is left out, and mixed precisions are rejected."""
+    from paper_1911_10747_amd import poolboil as pb
+    P = dict(W.BASE_PARAMS, Tc=0.07, rho_L=6.5, rho_V=0.38, rho_S=19.5)
+    cfg = lambda **kw: pb.make_config(**dict(P, **kw))
+    for prec, tall, slots in ((1, 36, 3072), (0, 28, 2048)):
+        w = pb.thermal_work_list([cfg(nx=4096, ny_fluid=2048, ny_solid=64, precision=prec)])
+        _cover(w, [(4096, 2112)])
+        rows = w[:, 3]
+        assert set(rows) == {tall, 8}
+        nshort = int((rows == 8).sum())
+        assert (rows[-nshort:] == 8).all() and (rows[:-nshort] == tall).all()
+        assert 0.5 * slots <= nshort <= 0.7 * slots, nshort
+        assert w[:, 2][rows == 8].min() > w[:, 2][rows == tall].max()     # the top rows
+    # explicit 28-row strips in FP32 get the tail too
+    w = pb.thermal_work_list([cfg(nx=4096, ny_fluid=2048, ny_solid=64, precision=1, thermal_tile=1)])
+    _cover(w, [(4096, 2112)])
+    assert set(w[:, 3]) == {28, 8} and w[-1, 3] == 8
+    # small domain: 8-row strips, 8 x 53
+    w = pb.thermal_work_list([cfg(nx=400, ny_fluid=400, ny_solid=20, precision=1)])
+    _cover(w, [(400, 420)])
+    assert len(w) == 8 * 53 and set(w[:, 3]) == {8}
+    # batch of auto-strip domains, with an isothermal seventh member
+    six = [cfg(nx=1000, ny_fluid=480, ny_solid=24, precision=1) for _ in range(6)]
+    iso = cfg(nx=300, ny_fluid=100, ny_solid=10, precision=1, flags=pb.PB_ISOTHERMAL)
+    w = pb.thermal_work_list(six + [iso])
+    _cover(w, [(1000, 504)] * 6)
+    assert not (w[:, 0] == 6).any()
+    assert set(w[:, 3]) == {16, 8}
+    short = w[w[:, 3] == 8]
+    assert set(short[:, 0]) == set(range(6)) and (w[-len(short):, 3] == 8).all()
+    # explicit strips on the first member decide for the batch
+    w = pb.thermal_work_list([cfg(nx=1000, ny_fluid=480, ny_solid=24, precision=1, thermal_tile=4)] + six[1:])
+    _cover(w, [(1000, 504)] * 6)
+    assert set(w[:, 3]) == {16, 8}
+    w = pb.thermal_work_list([cfg(nx=1000, ny_fluid=480, ny_solid=24, precision=1, thermal_tile=6)] + six[1:])
+    assert set(w[:, 3]) == {8}
+    with pytest.raises(pb.PbError):
+        pb.thermal_work_list([six[0], cfg(nx=100, ny_fluid=100, ny_solid=10, precision=0)])
