@@ -167,7 +167,11 @@ __device__ __forceinline__ FT encode_pop(int i, double fs, double rho_ref) {
         return fs;
 }
 
-// Where a node's outputs go: global pointers at element offset oidx.
+// Where a node's outputs go: global pointers at element offset oidx.  The
+// stores are non-temporal: the next reader is the next launch, after the whole
+// domain has streamed through L2, so keeping them out of L2 leaves it to the
+// halo re-reads (4096 x 2112, FP32: flow 191 -> 185 us, and the energy launch
+// after it 74.9 -> 71.9 us).
 template <typename FT>
 struct GlobalStore {
     FT PB_GAS *f;
@@ -175,11 +179,13 @@ struct GlobalStore {
     FT PB_GAS *vx;
     FT PB_GAS *vy;
     uint32_t plane, oidx;
-    __device__ __forceinline__ void pop(int i, FT v) const { (f + (uint32_t)i * plane)[oidx] = v; }
+    __device__ __forceinline__ void pop(int i, FT v) const {
+        __builtin_nontemporal_store(v, &(f + (uint32_t)i * plane)[oidx]);
+    }
     __device__ __forceinline__ void fields(double r, FT ux, FT uy) const {
-        rho[oidx] = (FT)r;
-        vx[oidx] = ux;
-        vy[oidx] = uy;
+        __builtin_nontemporal_store((FT)r, &rho[oidx]);
+        __builtin_nontemporal_store(ux, &vx[oidx]);
+        __builtin_nontemporal_store(uy, &vy[oidx]);
     }
 };
 
