@@ -222,9 +222,11 @@ def serving_legs(log):
     """Boiling-curve jobs: (1) 32 jobs of log-uniform size 128..1024 x 128..512
     (heater 1/20 of the height), superheat U[0.02, 0.30] Tc, 20000 steps, all
     submitted at once; (2) a Poisson stream of 48 jobs, sizes 64..2048 x
-    64..1024, 5000-20000 steps, arrival rate 4 jobs/s.  FP32-deviation
+    64..1024, 5000-20000 steps, 4 GiB of device memory for resident jobs, at
+    three loads relative to the FP32 capacity on these jobs.  FP32-deviation
     continuous batching against FP64 one job at a time, same jobs (the curve
-    also FP32 one job at a time, to separate batching from precision).  The
+    also FP32 one job at a time, to separate batching from precision), the
+    stream replayed at 0.5, 0.8 and 1.2 x the measured FP32 capacity.  The
     curve's batched run takes the tile shapes of the batch autotuner run on its
     job mix (outside the timed legs); the stream's batches take the tuned flow
     tile and the energy strips the library chooses for each batch's total size;
@@ -252,19 +254,31 @@ def serving_legs(log):
                                                                            for j in curve])),
                                 heat_flux_rel_diff_median=float(np.median(dq)), heat_flux_rel_diff_max=float(dq.max()),
                                 within_3pct=int((dq <= 0.03).sum()))
-    stream = W.job_stream(seed=0, n=48, rate_per_s=4.0)
-    log("serving: Poisson stream, 48 jobs, FP32 continuous batching")
-    # the stream's resident set changes from chunk to chunk: its batches take
-    # the tuned flow tile and energy strips the library sizes for each batch
-    s32, q32 = _serve_jobs(stream, 1, True, 32, 4 << 30, realtime=True, tiles=dict(tiles, thermal_tile=0))
-    log("serving: Poisson stream, 48 jobs, FP64 one at a time")
-    s64, q64 = _serve_jobs(stream, 0, False, 1, 4 << 30, realtime=True)
-    dq = np.abs(np.array(q32) - np.array(q64)) / np.maximum(np.abs(np.array(q64)), 1e-30)
     out["batched_tiles"] = dict(flow=list(tiles["tile"]), thermal=tiles["thermal_tile"],
                                 ms_per_step_curve_mix=round(tiles["ms_per_step"], 4))
-    out["poisson_stream"] = dict(rate_jobs_per_s=4.0, fp32_batched=s32, fp64_one_at_a_time=s64,
-                                 heat_flux_rel_diff_median=float(np.median(dq)),
-                                 heat_flux_rel_diff_max=float(dq.max()), within_3pct=int((dq <= 0.03).sum()))
+    # Poisson stream: one job mix (arrival gaps drawn at 1 job/s), replayed at
+    # 0.5, 0.8 and 1.2 x the FP32 capacity measured on the same jobs submitted
+    # at once.  The resident set changes from chunk to chunk, so the batches
+    # take the tuned flow tile and the energy strips the library sizes for
+    # each batch.
+    stream = W.job_stream(seed=0, n=48, rate_per_s=1.0)
+    stiles = dict(tiles, thermal_tile=0)
+    log("serving: Poisson stream jobs, FP32 capacity (all submitted at once)")
+    cap, _ = _serve_jobs(stream, 1, True, 32, 4 << 30, realtime=False, tiles=stiles)
+    cap_per_s = cap["jobs_per_hour"] / 3600.0
+    levels = []
+    for load in (0.5, 0.8, 1.2):
+        rate = load * cap_per_s
+        log(f"serving: Poisson stream, 48 jobs at {rate:.2f} jobs/s ({load} x capacity), FP32 continuous batching")
+        s32, q32 = _serve_jobs(stream, 1, True, 32, 4 << 30, realtime=True, time_scale=rate, tiles=stiles)
+        log(f"serving: Poisson stream, 48 jobs at {rate:.2f} jobs/s, FP64 one at a time")
+        s64, q64 = _serve_jobs(stream, 0, False, 1, 4 << 30, realtime=True, time_scale=rate)
+        dq = np.abs(np.array(q32) - np.array(q64)) / np.maximum(np.abs(np.array(q64)), 1e-30)
+        levels.append(dict(load=load, rate_jobs_per_s=round(rate, 3), fp32_batched=s32, fp64_one_at_a_time=s64,
+                           heat_flux_rel_diff_median=float(np.median(dq)), heat_flux_rel_diff_max=float(dq.max()),
+                           within_3pct=int((dq <= 0.03).sum())))
+    out["poisson_stream"] = dict(jobs=len(stream), mem_budget_gib=4, fp32_capacity=cap,
+                                 fp32_capacity_jobs_per_s=round(cap_per_s, 3), levels=levels)
     return out
 
 
