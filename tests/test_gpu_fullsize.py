@@ -1,7 +1,8 @@
 """Parity at the workload sizes, and the long-run heat-flux statistic.
 
 * 400x400 fluid + 400x20 heater (paper-scale job), FP64 and FP32-deviation
-  storage, 100 steps against the oracle, every field.
+  storage, 100 steps against the oracle, every field; the 100x100 + 100x10
+  pool after 2000 steps likewise.
 * 4096x2048 fluid + 4096x64 heater (roofline case) in the launch
   configuration the benchmark times (autotuned tiles are bit-identical to the
   default, checked elsewhere), FP32-deviation storage, 2 steps against the
@@ -49,6 +50,19 @@ def test_roofline_case_full_domain():
     m1 = dom.read(with_f=False)["rho"].sum()
     assert abs(m1 - m0) / m0 < 1e-9
     dom.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_pool_100x100_2000_steps(precision):
+    """The plain 100x100 + 100x10 pool (liquid below y = 40, 4 seeded +2% hot
+    spots, superheat 0.1 Tc) after 2000 steps, every field against the
+    oracle, with the 200-step bars (1e-11 FP64, 2e-5 FP32-deviation)."""
+    P, d, bc, rho, T = pool_case(100, 100, 10, superheat=0.1, n_spots=4, seed=0, y0=40)
+    g, o = run_pair(P, bc, rho, T, steps=2000, precision=precision, window=(1000, 2001, 10))
+    errs = compare(g, o)
+    print("C0 2000 steps prec", precision, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert all(v <= TOL[precision] for v in errs.values()), errs
+    assert g["flux"]["q_bottom_mean"] == pytest.approx(o["flux"]["q_bottom_mean"], rel=10 * TOL[precision])
 
 
 @pytest.mark.parametrize("superheat", [0.05, 0.2])
