@@ -242,6 +242,9 @@ def serving_legs(log):
     log(f"serving: batched FP32 tiles: flow {tiles['tile']}, thermal {tiles['thermal_tile']}")
     log("serving: boiling curve, 32 jobs, FP32 batched")
     b32, q32 = _serve_jobs(curve, 1, True, 64, 32 << 30, realtime=False, tiles=tiles)
+    # the whole job mix's algorithmic bytes over the batched run's wall clock
+    alg = sum(algorithmic_bytes(j["nx"], j["nyf"], j["nys"], 1) * j["steps"] for j in curve)
+    b32["hbm_frac_algorithmic"] = round(alg / b32["wall_s"] / 1e9 / HBM_PEAK_GBS, 4)
     log("serving: boiling curve, 32 jobs, FP32 one at a time")
     b32s, _ = _serve_jobs(curve, 1, False, 1, 32 << 30, realtime=False)
     log("serving: boiling curve, 32 jobs, FP64 one at a time")
