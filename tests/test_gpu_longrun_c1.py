@@ -1,11 +1,14 @@
 """Long runs at paper scale, the long-run bar for FP32 storage: a 400x400
 fluid over a 400x20 heater (liquid below y = 160) with either trigger of the
 workload (six seeded +2% hot spots, or a seeded +-1% per-column fluctuation of
-T_b for 3000 <= t < 15000) at superheats 0.05 .. 0.25 Tc for 20000 steps.  Boiling is chaotic, so the
+T_b for 3000 <= t < 15000) at superheats 0.05 .. 0.25 Tc, and the hot-spot
+pool at three seeded draws of the superheat from [0.05, 0.25] Tc, for 20000
+steps.  Boiling is chaotic, so the
 FP32-deviation GPU runs and the FP64 oracle are compared only through the
 time-mean wall heat flux (Eq. 38 of Eq. 36, steps 10000..20000 every 10),
 within 3% per superheat.  The oracle means are stored in
-tests/golden/longrun_c1_oracle.json and longrun_c1_fluct_oracle.json, written
+tests/golden/longrun_c1_oracle.json, longrun_c1_fluct_oracle.json and
+longrun_c1_draws_oracle.json, written
 by make_longrun_c1.py beside them (which runs the oracle and nothing else,
 about an hour on eight cores per file)."""
 import json
@@ -21,7 +24,8 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 GOLDEN = {t: os.path.join(os.path.dirname(__file__), "golden", f)
-          for t, f in (("spots", "longrun_c1_oracle.json"), ("fluctuation", "longrun_c1_fluct_oracle.json"))}
+          for t, f in (("spots", "longrun_c1_oracle.json"), ("fluctuation", "longrun_c1_fluct_oracle.json"),
+                       ("draws", "longrun_c1_draws_oracle.json"))}
 
 
 def _run(rec, precision):
@@ -44,7 +48,7 @@ def _run(rec, precision):
     return out
 
 
-@pytest.mark.parametrize("trigger", ["spots", "fluctuation"])
+@pytest.mark.parametrize("trigger", ["spots", "fluctuation", "draws"])
 def test_c1_long_run_mean_heat_flux_within_3pct(trigger):
     if not os.path.exists(GOLDEN[trigger]):
         pytest.skip("oracle means not written yet (tests/golden/make_longrun_c1.py)")
@@ -59,7 +63,7 @@ def test_c1_long_run_mean_heat_flux_within_3pct(trigger):
         assert rel <= 0.03
 
 
-@pytest.mark.parametrize("trigger", ["spots", "fluctuation"])
+@pytest.mark.parametrize("trigger", ["spots", "fluctuation", "draws"])
 def test_c1_long_run_fp64_storage_tracks_the_oracle(trigger):
     """FP64 storage differs from the oracle only in rounding order, and over
     20000 steps of boiling the time-mean heat flux stays within 1e-8 of the
