@@ -2,16 +2,19 @@
 """Benchmark of the pool-boiling LBM step on one MI355X.
 
 Default workload: the roofline case, a 4096x2048 fluid domain over a 4096x64
-heater, FP32-deviation population storage; the flow step computes in FP64,
-the energy equation in FP32 increments over FP64 T (with FP64 EOS derivative
-and stage-1 differences); one +2% hot spot per 64 heater columns (seed 0), heater-bottom superheat
-0.1 Tc, heat flux sampled every 10 steps.  A step is one full time step of the
+heater, FP32-deviation population storage (populations as deviations from
+w_i rho, rho and v in FP32, T in FP64); the flow step computes in FP64, the
+energy equation in FP32 increments over FP64 T (with FP64 EOS derivative and
+stage-1 differences); one +2% hot spot per 64 heater columns (seed 0),
+heater-bottom superheat 0.1 Tc, heat flux sampled every 10 steps.  A step is one full time step of the
 method (flow launch + thermal launch [+ flux sample]).  Inputs are resident in
 HBM when the timed region starts.
 
 Prints ONE JSON line with MLUPS (fluid-node updates per second), the roofline
 of the step against the 8 TB/s HBM peak and the FP64 oracle timed on the host
-on a bounded sample of the same workload.
+on a bounded sample of the same workload; beside them the serving legs
+(32-job boiling curve, Poisson job stream at three loads) and the smaller
+single-domain set-ups.
 """
 import argparse
 import json
