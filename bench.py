@@ -138,7 +138,7 @@ def cpu_baseline(nx, nyf, nys, steps):
     """The FP64 oracle, as it stands, on `steps` steps of the same workload
     (serial C, one core)."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
-    import workloads as W
+    from paper_1911_10747_amd import workloads as W
     from oracle import eos, orc
     P = dict(W.BASE_PARAMS)
     Tc = eos.critical_temperature(P["a"], P["b"], P["R"])
@@ -235,7 +235,7 @@ def serving_legs(log):
     tile and the energy strips the library chooses for each batch's total size;
     a job run alone takes the library's choice for its size."""
     import numpy as np
-    import workloads as W
+    from paper_1911_10747_amd import workloads as W
     from paper_1911_10747_amd import autotune, presets
     out = {}
     curve = W.batch_jobs(seed=0, n=32, steps=20000)

@@ -14,15 +14,18 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "orc_step.c")
-LIB = os.path.join(HERE, "liborc.so")
+# ORC_LIB names another build of the same source (the mutation tests load a
+# copy of the oracle with one planted mistake this way)
+LIB = os.environ.get("ORC_LIB") or os.path.join(HERE, "liborc.so")
 
 
-def build(force=True):
+def build(force=True, src=SRC, out=None):
     """Compile the oracle with plain gcc, no fast-math, no FP contraction."""
-    if force or not os.path.exists(LIB):
+    out = LIB if out is None else out
+    if force or not os.path.exists(out):
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-                               "-o", LIB, SRC, "-lm"])
-    return LIB
+                               "-o", out, src, "-lm"])
+    return out
 
 
 class Params(C.Structure):

@@ -13,7 +13,7 @@ import math
 
 import numpy as np
 
-import workloads as W
+from . import workloads as W
 
 from . import poolboil as pb
 from . import presets

@@ -5,7 +5,8 @@ spots) at superheats 0.05 .. 0.25 Tc, 20000 steps each; with `fluctuation`,
 longrun_c1_fluct_oracle.json for the same pool with a uniform T_b replaced by
 a seeded +-1% per-column fluctuation for 3000 <= t < 15000; with `draws`,
 longrun_c1_draws_oracle.json for the hot-spot pool at three superheats drawn
-uniformly from [0.05, 0.25] Tc (seed 2024).  Calls only the oracle (one
+uniformly from [0.05, 0.25] Tc (seed 2024).  The records were written with
+varpi = 0.1 (Eq. 9), which each case names.  Calls only the oracle (one
 process per superheat); about an hour on eight cores for five superheats.
 
     python tests/golden/make_longrun_c1.py [fluctuation | draws]
@@ -22,10 +23,10 @@ sys.path.insert(0, os.path.join(os.path.dirname(HERE), ".."))
 
 SUPERHEATS = [0.05, 0.10, 0.15, 0.20, 0.25]
 CASES = {
-    "spots": (dict(nx=400, nyf=400, nys=20, n_spots=6, seed=11, y0=160), "longrun_c1_oracle.json"),
+    "spots": (dict(nx=400, nyf=400, nys=20, n_spots=6, seed=11, y0=160, varpi=0.1), "longrun_c1_oracle.json"),
     "fluctuation": (dict(nx=400, nyf=400, nys=20, n_spots=0, seed=11, y0=160, trigger="fluctuation", rel=0.01,
-                         t0=3000, t1=15000), "longrun_c1_fluct_oracle.json"),
-    "draws": (dict(nx=400, nyf=400, nys=20, n_spots=6, seed=11, y0=160), "longrun_c1_draws_oracle.json"),
+                         t0=3000, t1=15000, varpi=0.1), "longrun_c1_fluct_oracle.json"),
+    "draws": (dict(nx=400, nyf=400, nys=20, n_spots=6, seed=11, y0=160, varpi=0.1), "longrun_c1_draws_oracle.json"),
 }
 
 

@@ -5,7 +5,7 @@ import functools
 
 import numpy as np
 
-import workloads as W
+from paper_1911_10747_amd import workloads as W
 from oracle import eos
 
 
@@ -52,12 +52,14 @@ def pool_case(nx, nyf, nys, superheat=0.1, n_spots=4, seed=0, y0=None, gamma_fra
 
 def c1_case(case, superheat):
     """The paper-scale long-run case of a stored record: `case` holds nx, nyf,
-    nys, seed, y0 and n_spots (spot trigger) or, with trigger "fluctuation",
+    nys, seed, y0, optionally the varpi it was written with, and n_spots (spot
+    trigger) or, with trigger "fluctuation",
     a uniform T_b replaced by the seeded per-column T_b (1 + rel xi_x) for
     t0 <= t < t1 (the workload's +-1% fluctuation)."""
     fluct = case.get("trigger") == "fluctuation"
+    over = {k: case[k] for k in ("varpi",) if k in case}
     P, d, bc, rho, T = pool_case(case["nx"], case["nyf"], case["nys"], superheat=superheat,
-                                 n_spots=0 if fluct else case["n_spots"], seed=case["seed"], y0=case["y0"])
+                                 n_spots=0 if fluct else case["n_spots"], seed=case["seed"], y0=case["y0"], **over)
     if fluct:
         bc.update(Tb_alt=W.fluct_Tb(case["nx"], bc["Tb"][0], case["seed"], rel=case["rel"]),
                   t0=case["t0"], t1=case["t1"])

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 from scipy import integrate
 
-import workloads as W
+from paper_1911_10747_amd import workloads as W
 from conftest import golden
 from helpers import derived, params, pool_case
 from oracle import eos, orc
@@ -502,19 +502,157 @@ def test_checkpoint_resume_is_exact(oracle_lib):
 
 
 # ------------------------------------------------------------ physical pins (slow-ish)
-def test_flat_interface_coexistence(oracle_lib):
-    """Section 3.1: a flat liquid slab at T_sat relaxes to bulk densities close
-    to the Maxwell pair (the varpi term of Eq. 9 exists to achieve this).
-    Tolerance: 3% on rho_L, 15% on rho_V (uncalibrated varpi)."""
+@pytest.mark.parametrize("a, varpi", [(2 / 49, W.BASE_PARAMS["varpi"]), (3 / 49, W.VARPI_A_3_49)])
+def test_flat_interface_coexistence(oracle_lib, a, varpi):
+    """Section 3.1: a flat liquid slab at T_sat in a periodic box without
+    gravity relaxes to bulk densities equal to the Maxwell pair of Eq. 13 (the
+    varpi term of Eq. 9 exists to achieve this).  varpi is not printed; the
+    value used is the one that makes the vapour match (calibrated separately
+    for a = 2/49 and a = 3/49).  Bulk liquid within 0.05%, bulk vapour within
+    0.5%, both slab interiors flat; without the varpi term the vapour density
+    is 70% low, so the term is what brings it to Maxwell."""
     nx, ny = 2, 80
-    P, d = params(nx, ny, 0, periodic_y=1, isothermal=1)
+    P, d = params(nx, ny, 0, periodic_y=1, isothermal=1, g=0.0, a=a, varpi=varpi)
     dom = orc.Domain(**P)
     dom.set_bc(d["Tsat"])
     dom.set_fields(W.slab_rho(nx, ny, 20.0, 60.0, d["rho_L"], d["rho_V"], width=4.0), np.full((ny, nx), d["Tsat"]))
     assert dom.step(15000) == 0
     rho = dom.read()["rho"][:, 0]
-    assert rho[40] == pytest.approx(d["rho_L"], rel=0.03)
-    assert rho[0] == pytest.approx(d["rho_V"], rel=0.15)
+    liquid, vapour = rho[32:49], np.r_[rho[:9], rho[72:]]
+    np.testing.assert_allclose(liquid, d["rho_L"], rtol=5e-4)
+    np.testing.assert_allclose(vapour, d["rho_V"], rtol=5e-3)
+    # without gravity the slab stays where it started, centred on row 40
+    prof = rho - d["rho_V"]
+    assert np.sum(prof * np.arange(ny)) / np.sum(prof) == pytest.approx(40.0, abs=1e-3)
+    P0, _ = params(nx, ny, 0, periodic_y=1, isothermal=1, g=0.0, a=a, varpi=0.0)
+    dom0 = orc.Domain(**P0)
+    dom0.set_bc(d["Tsat"])
+    dom0.set_fields(W.slab_rho(nx, ny, 20.0, 60.0, d["rho_L"], d["rho_V"], width=4.0), np.full((ny, nx), d["Tsat"]))
+    assert dom0.step(15000) == 0
+    assert dom0.read()["rho"][0, 0] < 0.5 * d["rho_V"]
+
+
+def _moment_polynomials():
+    """Rows of the moment basis of Eq. 6 written from their physical meaning
+    (density, energy e, energy square epsilon, momentum j, energy flux q,
+    stress p_xx, p_xy), as polynomials of the lattice velocity, with the rate
+    Eq. 3 gives each: s_0 = s_j = 1, s_e = s_epsilon, s_q, s_nu (stress)."""
+    e2 = EX * EX + EY * EY
+    return {
+        "e": (-4 + 3 * e2, "s_e"),
+        "epsilon": (4 - 10.5 * e2 + 4.5 * e2 * e2, "s_e"),
+        "q_x": ((-5 + 3 * e2) * EX, "s_q"),
+        "q_y": ((-5 + 3 * e2) * EY, "s_q"),
+        "p_xx": (EX * EX - EY * EY, "s_nu"),
+        "p_xy": (EX * EY, "s_nu"),
+    }
+
+
+def test_relaxation_rates_act_on_their_moments(oracle_lib):
+    """Eq. 3 assigns the rates to moment rows: Lambda = diag(s_0, s_e, s_epsilon,
+    s_j, s_q, s_j, s_q, s_nu, s_nu) with s_e = s_epsilon and, by Eq. 5,
+    s_nu = 1/tau(rho), tau interpolated linearly in rho between
+    tau(rho_V) = 3 nu_V + 1/2 = 1.0 and tau(rho_L) = 3 nu_L + 1/2 = 0.8 (Eq. 4 with
+    the printed viscosities).  At rest with no force, a deviation from the rest
+    equilibrium along one physical moment (e.g. the stress e_x^2 - e_y^2) is an
+    eigenvector of the collision: f* - w rho = (1 - s_k)(f - w rho).  Distinct
+    s_e, s_q and tau_L != tau_V, so swapped rows or swapped interpolation
+    endpoints fail."""
+    tau_V = 3 * GOLD["nu_V_printed"][0] + 0.5
+    tau_L = 3 * GOLD["nu_L_printed"][0] + 0.5
+    P, d = params(4, 4, 4, s_e=0.7, s_q=1.3, varpi=0.0)
+    assert (P["tau_L"], P["tau_V"]) == pytest.approx((tau_L, tau_V), rel=1e-12)
+    p = orc.make_params(**P)
+    rho_mid = 0.5 * (d["rho_L"] + d["rho_V"])
+    for rho, tau in ((d["rho_V"], tau_V), (d["rho_L"], tau_L), (rho_mid, 0.5 * (tau_L + tau_V))):
+        rate = {"s_e": 0.7, "s_q": 1.3, "s_nu": 1.0 / tau}
+        for name, (poly, which) in _moment_polynomials().items():
+            assert abs(np.sum(poly)) < 1e-12 and abs(np.sum(poly * EX)) < 1e-12 and abs(np.sum(poly * EY)) < 1e-12
+            dev = 1e-3 * rho * poly / np.sum(poly * poly)
+            f = WL * rho + dev
+            out = orc.collide_node(p, f, rho, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0)
+            np.testing.assert_allclose(out - WL * rho, (1.0 - rate[which]) * dev, rtol=0, atol=1e-15 * rho,
+                                       err_msg=f"{name} at rho = {rho}")
+
+
+@pytest.mark.parametrize("phase", ["liquid", "vapour"])
+def test_shear_wave_decays_with_printed_viscosity(oracle_lib, phase):
+    """Section 3.1 prints nu_L = 0.1 and nu_V = 0.5/3; Eqs. 4-5 turn them into
+    the stress relaxation rate.  A shear wave u_x = U sin(2 pi y / 64) in a
+    periodic box of uniform density (no interaction force, no gravity) decays
+    as exp(-nu k^2 t): the measured nu must be the printed one of that phase
+    (to 0.3%, the O(k^2) lattice correction at this wavelength is 0.08%)."""
+    nx, ny, n, U = 2, 64, 1000, 1e-3
+    P, d = params(nx, ny, 0, periodic_y=1, isothermal=1, g=0.0)
+    rho0, nu = (d["rho_L"], GOLD["nu_L_printed"][0]) if phase == "liquid" else (d["rho_V"], GOLD["nu_V_printed"][0])
+    k = 2 * np.pi / ny
+    y = np.arange(ny)
+    ux = U * np.sin(k * y)[:, None] * np.ones((1, nx))
+    eu = EX[:, None, None] * ux
+    f = WL[:, None, None] * rho0 * (1 + 3 * eu + 4.5 * eu ** 2 - 1.5 * ux ** 2)
+    dom = orc.Domain(**P)
+    dom.set_bc(d["Tsat"])
+    dom.set_state(f, np.full((ny, nx), d["Tsat"]), 0, rho0)
+    amp0 = 2.0 / ny * np.sum(dom.read()["ux"][:, 0] * np.sin(k * y))
+    assert dom.step(n) == 0
+    r = dom.read()
+    amp1 = 2.0 / ny * np.sum(r["ux"][:, 0] * np.sin(k * y))
+    assert -math.log(amp1 / amp0) / (n * k * k) == pytest.approx(nu, rel=3e-3)
+    np.testing.assert_allclose(r["rho"], rho0, rtol=1e-9)
+
+
+def test_eq36_second_order_on_quadratic_heater_profile(oracle_lib):
+    """Eq. 36: the heater-bottom gradient is the one-sided second-order
+    difference (4 T(x,1) - T(x,2) - 3 T(x,0)) / 2, exact for T quadratic in y.
+    A heater profile T = A + B y + C y^2 (C != 0, different per column) held
+    fixed (isothermal run) must give q_bottom = -lambda_S * mean_x B(x) to
+    round-off; a first-order difference would give -lambda_S (B + C)."""
+    nx, nyf, nys = 6, 5, 8
+    P, d = params(nx, nyf, nys, isothermal=1, g=0.0)
+    x = np.arange(nx)
+    A = d["Tsat"] + 0.1 * d["Tc"]
+    B = -2e-3 * (1.0 + 0.1 * x)
+    C = 4e-5 * (1.0 + 0.3 * x)
+    T = np.full((nys + nyf, nx), d["Tsat"])
+    ys = np.arange(nys)[:, None]
+    T[:nys] = A + B[None, :] * ys + C[None, :] * ys * ys
+    gam = np.full(nx, -d["psi_L"])
+    dom = orc.Domain(**P)
+    dom.set_bc(d["Tsat"], T[0].copy(), gamma_bot=gam, gamma_top=gam)
+    f = WL[:, None, None] * d["rho_L"] * np.ones((9, nyf, nx))
+    dom.set_state(f, T, 0, d["rho_L"])
+    dom.flux_window(1, 2, 1)
+    assert dom.step(1) == 0
+    hf = dom.heat_flux()
+    assert hf["n_samples"] == 1
+    assert hf["q_bottom_inst"] == pytest.approx(-P["lambda_S"] * B.mean(), rel=1e-12)
+    assert abs(hf["q_bottom_inst"] + P["lambda_S"] * (B + C).mean()) > 1e-3 * abs(hf["q_bottom_inst"])
+
+
+@pytest.mark.parametrize("fm_only", [0, 1])
+def test_varpi_force_reading_rest_beside_neutral_wall(oracle_lib, fm_only):
+    """Reading of Eq. 9 (which force enters the varpi term).  A liquid at rest
+    at uniform density between walls whose adhesion is neutral
+    (gamma = -psi(rho_L), Eq. 14) feels no total force: F_m + F_ads = 0 on the
+    wall rows.  With the whole interaction F_m + F_ads in the varpi term (this
+    build's reading) the rest state is a fixed point; with F_m of Eq. 11 alone
+    (the printed symbol), F_m != 0 on the wall rows puts a source into moments
+    1-2 there and the liquid starts to move."""
+    nx, nyf, nys = 7, 9, 4
+    P, d = params(nx, nyf, nys, g=0.0, isothermal=1, varpi_fm_only=fm_only)
+    dom = orc.Domain(**P)
+    gam = np.full(nx, -d["psi_L"])
+    dom.set_bc(d["Tsat"], np.full(nx, d["Tsat"]), gamma_bot=gam, gamma_top=gam)
+    dom.set_fields(np.full((nyf, nx), d["rho_L"]), np.full((nyf + nys, nx), d["Tsat"]))
+    f0 = dom.read()["f"]
+    assert dom.step(50) == 0
+    r = dom.read()
+    change = np.max(np.abs(r["f"] - f0)) / np.max(np.abs(f0))
+    speed = max(np.abs(r["ux"]).max(), np.abs(r["uy"]).max())
+    if fm_only:
+        assert change > 1e-2 and speed > 1e-4
+    else:
+        assert change < 1e-13 and speed < 1e-14
 
 
 @pytest.mark.slow
