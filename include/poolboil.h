@@ -207,16 +207,34 @@ double pb_rho_bar(const pb_domain *dom);          /* rho_bar of Eq. 15      */
  * the precision; they are stepped in lock-step on `stream`, or on a stream of
  * the batch's own if it is NULL, each pb_batch_step ordered after the work
  * already queued on the domains' streams and before work queued there later.
- * Per-node arithmetic does not depend on the batch, so each domain's result is
- * bit-identical to stepping it alone.  Tile shapes come from the first
- * domain's configuration; when every domain has thermal_tile = 0 the energy
- * strips are chosen for the batch's total size (pb_thermal_strip_rows's rule
- * over all members).  persistent_blocks > 0 caps the grid (blocks then loop
- * over the work-list).  The domains must outlive the batch. */
+ * Each member keeps its own time t (members may have started at different
+ * times).  Per-node arithmetic does not depend on the batch, so each domain's
+ * result is bit-identical to stepping it alone.  Tile shapes come from the
+ * first member's configuration; when every member has thermal_tile = 0 the
+ * energy strips are chosen for the batch's total size (pb_thermal_strip_rows's
+ * rule over all members).  persistent_blocks > 0 caps the grid (blocks then
+ * loop over the work-list).  A domain must stay alive while it is a member. */
 int pb_batch_create(pb_domain *const *doms, int32_t n, int32_t steps_per_graph, int32_t persistent_blocks,
                     void *stream, pb_batch **out);
 int pb_batch_step(pb_batch *batch, int64_t n);
 void pb_batch_destroy(pb_batch *batch);
+
+/* Membership changes between steps, for continuous batching (jobs join and
+ * leave a batch that keeps running).  pb_batch_add appends a domain (fields
+ * set, the batch's precision, not already a member); pb_batch_remove takes one
+ * out.  The launches' work lists and descriptor table are rebuilt on the host
+ * and uploaded on the batch stream, ordered after the steps already queued
+ * (those still step the previous members); no member stream is synchronised,
+ * and the captured step graph is captured again at the next graph-length step.
+ * A batch may become empty (pb_batch_step then does nothing).  Work queued
+ * before a removal still reaches the removed domain and its stream waits for
+ * that work, so the domain may be destroyed right after pb_batch_remove.
+ * Errors: PB_EINVAL (NULL, not a member / already a member, other precision),
+ * PB_ESTATE (no fields), PB_ENOMEM, PB_EDEVICE; on error the membership is
+ * unchanged. */
+int pb_batch_add(pb_batch *batch, pb_domain *dom);
+int pb_batch_remove(pb_batch *batch, pb_domain *dom);
+int32_t pb_batch_size(const pb_batch *batch);   /* members, or -1 for NULL */
 
 /* Host helpers for configuration (no device work): the critical temperature
  * implied by a = 0.45724 R^2 Tc^2/Pc and b = 0.0778 R Tc/Pc (Section 2.1), and

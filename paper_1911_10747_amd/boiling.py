@@ -24,7 +24,7 @@ import time
 
 import numpy as np
 
-import workloads as W
+from . import workloads as W
 
 from . import poolboil as pb
 from . import presets
@@ -39,7 +39,7 @@ HEATER_ANGLE = 55.0
 
 def paper_params():
     """Physical parameters of the paper's boiling runs (Section 3.1)."""
-    return dict(W.BASE_PARAMS, a=A_PAPER, g=5e-5)
+    return dict(W.BASE_PARAMS, a=A_PAPER, g=5e-5, varpi=W.VARPI_A_3_49)
 
 
 def paper_derived(P=None):
@@ -92,6 +92,27 @@ def calibrated_gammas(P, d, **kw):
     return dict(zip(angles, (float(v) for v in g)))
 
 
+def job_inputs(superheat, gammas, nx=NX, nyf=NYF, nys=NYS, trigger="spots", P=None, d=None):
+    """Parameters, boundary data and initial fields of one boiling-curve job:
+    (params with nx, nyf, nys and every physical constant, bc keyword
+    arguments of set_bc, rho [nyf][nx], T [nys + nyf][nx]).  Liquid in the
+    lower half of the pool at the Maxwell density, T = T_sat except the
+    heater bottom at T_sat + superheat Tc; the heater wall at 55 deg with the
+    three spots (trigger "spots"), or a uniform 55 deg wall with the Section
+    3.2 sinusoid on T_b for 3000 <= t < 15000 (trigger "fluctuation")."""
+    P = paper_params() if P is None else P
+    d = paper_derived(P) if d is None else d
+    params = dict(P, nx=nx, nyf=nyf, nys=nys, Tc=d.Tc, rho_L=d.rho_L, rho_V=d.rho_V,
+                  rho_S=W.RHO_S_OVER_RHO_L * d.rho_L)
+    gam = heater_gamma(nx, gammas) if trigger == "spots" else np.full(nx, gammas[HEATER_ANGLE])
+    Tb = np.full(nx, d.Tsat + superheat * d.Tc)
+    bc = dict(T_top=d.Tsat, Tb=Tb, gamma_bot=gam, gamma_top=np.full(nx, -d.psi_V))
+    if trigger == "fluctuation":
+        bc.update(Tb_alt=W.sinus_Tb(nx, Tb[0], 0.02 * d.Tc, nx / 2.0), t0=3000, t1=15000)
+    rho = W.layered_rho(nx, nyf, nyf // 2, d.rho_L, d.rho_V)
+    return params, bc, rho, W.thermal_init(nx, nys, nyf, d.Tsat, Tb)
+
+
 def run_curve(superheats, steps=42000, t_a=25000, every=10, precision=pb.PB_FP32_DEV, gammas=None, sigma=None,
               nx=NX, nyf=NYF, nys=NYS, trigger="spots", log=None):
     """One job per superheat (units of Tc), all stepped in one batched launch
@@ -109,19 +130,15 @@ def run_curve(superheats, steps=42000, t_a=25000, every=10, precision=pb.PB_FP32
         gammas = calibrated_gammas(P, d)
     if sigma is None:
         sigma = wetting.surface_tension(params=P, d=d)[0]
-    cfg = dict(P, Tc=d.Tc)
-    gam = heater_gamma(nx, gammas) if trigger == "spots" else np.full(nx, gammas[HEATER_ANGLE])
     doms = []
     try:
         for sh in superheats:
-            c = pb.make_config(nx=nx, ny_fluid=nyf, ny_solid=nys, precision=precision, flags=0, rho_L=d.rho_L,
-                               rho_V=d.rho_V, rho_S=W.RHO_S_OVER_RHO_L * d.rho_L, **cfg)
+            cp, bc, rho, T = job_inputs(sh, gammas, nx=nx, nyf=nyf, nys=nys, trigger=trigger, P=P, d=d)
+            c = pb.make_config(nx=nx, ny_fluid=nyf, ny_solid=nys, precision=precision, flags=0,
+                               **{k: v for k, v in cp.items() if k not in ("nx", "nyf", "nys")})
             dom = pb.Domain(c)
-            Tb = np.full(nx, d.Tsat + sh * d.Tc)
-            alt = dict(Tb_alt=W.sinus_Tb(nx, Tb[0], 0.02 * d.Tc, nx / 2.0), t0=3000, t1=15000) \
-                if trigger == "fluctuation" else {}
-            dom.set_bc(d.Tsat, Tb, gamma_bot=gam, gamma_top=np.full(nx, -d.psi_V), **alt)
-            dom.set_fields(W.layered_rho(nx, nyf, nyf // 2, d.rho_L, d.rho_V), W.thermal_init(nx, nys, nyf, d.Tsat, Tb))
+            dom.set_bc(**bc)
+            dom.set_fields(rho, T)
             dom.flux_window(t_a, steps + 1, every)
             doms.append(dom)
         batch = pb.Batch(doms, steps_per_graph=500)

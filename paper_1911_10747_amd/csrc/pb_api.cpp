@@ -139,6 +139,16 @@ int validate(const pb_config *c) {
     if (c->nx < 1 || c->ny_fluid < 1) return fail(PB_EINVAL, "nx and ny_fluid must be >= 1");
     if (c->nx > (1 << 20) || c->ny_fluid > (1 << 20) || c->ny_solid > (1 << 20))
         return fail(PB_EINVAL, "domain dimension above 2^20");
+    {
+        // the kernels address a domain's arrays with 32-bit element offsets:
+        // nine population planes, and the thermal rows
+        const uint64_t pitch = align_up((size_t)c->nx, 64);
+        if (9ull * (uint64_t)c->ny_fluid * pitch >= (1ull << 32) ||
+            (uint64_t)(c->ny_fluid + c->ny_solid) * pitch >= (1ull << 32))
+            return fail(PB_EINVAL, "domain of %d x (%d + %d) nodes exceeds 32-bit element offsets "
+                        "(9 * ny_fluid * pitch and (ny_fluid + ny_solid) * pitch must stay below 2^32)",
+                        c->nx, c->ny_fluid, c->ny_solid);
+    }
     if (c->precision != PB_FP64 && c->precision != PB_FP32_DEV) return fail(PB_EINVAL, "unknown precision %d", c->precision);
     if (c->flags & ~0x1Fu) return fail(PB_EINVAL, "unknown flag bits 0x%x", c->flags);
     const bool pery = (c->flags & PB_PERIODIC_Y) != 0;
@@ -265,23 +275,40 @@ struct pb_domain {
     bool fields_set = false;
     int fvar = 0, tvar = 0;
     int nt_flow = 0, nt_th = 0;
+    int device = 0;              // the GPU the domain lives on
     PbTile *dtiles_flow = nullptr, *dtiles_th = nullptr;
     std::vector<double> Tb, Tba, gb, gt;
-    double *rd = nullptr;        // read-back staging (lazy)
+    double *rd = nullptr;        // read-back staging of pb_read_fields (lazy)
 };
 
 struct pb_batch {
     std::vector<pb_domain *> doms;
     hipStream_t stream = nullptr;
+    bool owns_stream = false;
     int prec = 0, fvar = 0, tvar = 0;
     int nt_flow = 0, nt_th = 0, grid_flow = 0, grid_th = 0;
-    int spg = 0;
+    int spg = 0, persistent = 0;
+    // device tables of the launches, one buffer: descriptor pointers, flow
+    // tiles, energy strips; written from the pinned staging copy htab by an
+    // upload on the batch stream, so they change in stream order
+    char *dtab = nullptr, *htab = nullptr;
+    size_t tab_cap = 0, htab_cap = 0;
     PbDesc **dptrs = nullptr;
     PbTile *dtiles_flow = nullptr, *dtiles_th = nullptr;
+    hipEvent_t ev_upload = nullptr;   // after the last upload: htab may be rewritten once it has passed
+    bool upload_pending = false;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     std::vector<char> graph_flux;   // steps of the captured graph that launch the flux sample
-    bool owns_stream = false;
+    // graphs and table buffers replaced by a membership change, released once
+    // the work queued before the change (event `done`) has finished
+    struct Retired {
+        hipGraphExec_t exec;
+        hipGraph_t graph;
+        char *tab;
+        hipEvent_t done;
+    };
+    std::vector<Retired> retired;
     hipEvent_t ev_batch = nullptr, ev_dom = nullptr;
     std::vector<hipStream_t> dom_streams;   // distinct member streams
 };
@@ -428,6 +455,10 @@ int pb_create_domain(const pb_config *cfg, void *stream, void *dev_mem, size_t d
     d->nr = cfg->ny_fluid + cfg->ny_solid;
     d->fvar = flow_variant_of(*cfg);
     d->tvar = thermal_variant_of(*cfg);
+    if (hipGetDevice(&d->device) != hipSuccess) {
+        delete d;
+        return fail(PB_EDEVICE, "no current device");
+    }
     if (dev_mem) {
         if (dev_bytes < d->L.total) {
             delete d;
@@ -655,20 +686,22 @@ int pb_sync(pb_domain *d) {
     return PB_OK;
 }
 
-int pb_read_fields(pb_domain *d, double *rho, double *ux, double *uy, double *T, double *f) {
-    int rc = check_dom(d);
-    if (rc) return rc;
-    if (!d->fields_set) return fail(PB_ESTATE, "pb_set_fields was not called");
+}  // extern "C"
+
+namespace {
+
+// Read-back through FP64 staging planes at `stage` (12 x ny_fluid x pitch
+// doubles: f, rho, v_x, v_y): the flow kernel in read mode rebuilds f(t) and
+// forms rho(t), v(t) there, then the planes are copied to the host.
+int read_through(pb_domain *d, double *stage, double *rho, double *ux, double *uy, double *T, double *f) {
     const int nyf = d->cfg.ny_fluid;
     const size_t nf = (size_t)nyf * d->pitch;
-    PB_HIP(hipStreamSynchronize(d->stream));
-    if (!d->rd) {
-        if (hipMalloc((void **)&d->rd, 12 * nf * sizeof(double)) != hipSuccess)
-            return fail(PB_ENOMEM, "read staging allocation failed");
-        d->hd.rd_f = d->rd;
-        d->hd.rd_rho = d->rd + 9 * nf;
-        d->hd.rd_vx = d->rd + 10 * nf;
-        d->hd.rd_vy = d->rd + 11 * nf;
+    int rc;
+    if (d->hd.rd_f != stage) {
+        d->hd.rd_f = stage;
+        d->hd.rd_rho = stage + 9 * nf;
+        d->hd.rd_vx = stage + 10 * nf;
+        d->hd.rd_vy = stage + 11 * nf;
         if ((rc = upload_desc(d))) return rc;
     }
     if (rho || ux || uy || f) {
@@ -684,6 +717,21 @@ int pb_read_fields(pb_domain *d, double *rho, double *ux, double *uy, double *T,
             if ((rc = copy_rows_d2h(d, f + (size_t)i * nyf * d->cfg.nx, d->hd.rd_f + (size_t)i * nf, nyf))) return rc;
     PB_HIP(hipStreamSynchronize(d->stream));
     return PB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pb_read_fields(pb_domain *d, double *rho, double *ux, double *uy, double *T, double *f) {
+    int rc = check_dom(d);
+    if (rc) return rc;
+    if (!d->fields_set) return fail(PB_ESTATE, "pb_set_fields was not called");
+    const size_t nf = (size_t)d->cfg.ny_fluid * d->pitch;
+    PB_HIP(hipStreamSynchronize(d->stream));
+    if (!d->rd && hipMalloc((void **)&d->rd, 12 * nf * sizeof(double)) != hipSuccess)
+        return fail(PB_ENOMEM, "read staging allocation failed");
+    return read_through(d, d->rd, rho, ux, uy, T, f);
 }
 
 int pb_flux_window(pb_domain *d, int64_t t_a, int64_t t_b, int32_t every) {
@@ -777,6 +825,139 @@ int64_t pb_time(const pb_domain *d) { return d ? d->t : -1; }
 double pb_rho_bar(const pb_domain *d) { return d ? d->hd.rho_bar : 0.0; }
 
 // ------------------------------------------------------------------ batches
+namespace {
+
+// Release what a membership change replaced, once the work queued before the
+// change has finished (all = true: wait for it; used when the batch goes).
+void batch_reap(pb_batch *b, bool all) {
+    std::vector<pb_batch::Retired> keep;
+    for (pb_batch::Retired &r : b->retired) {
+        if (!all && hipEventQuery(r.done) != hipSuccess) {
+            keep.push_back(r);
+            continue;
+        }
+        if (all) (void)hipEventSynchronize(r.done);
+        if (r.exec) (void)hipGraphExecDestroy(r.exec);
+        if (r.graph) (void)hipGraphDestroy(r.graph);
+        if (r.tab) (void)hipFree(r.tab);
+        (void)hipEventDestroy(r.done);
+    }
+    b->retired.swap(keep);
+}
+
+// Retire the captured step graph and, if given, a table buffer: they stay
+// alive until the work already queued on the batch stream has run.
+int batch_retire(pb_batch *b, char *tab) {
+    if (!b->gexec && !tab) return PB_OK;
+    pb_batch::Retired r{b->gexec, b->graph, tab, nullptr};
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    if (hipEventCreateWithFlags(&r.done, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(r.done, b->stream) != hipSuccess) {
+        // cannot order the release: wait for the batch instead
+        (void)hipStreamSynchronize(b->stream);
+        if (r.done) (void)hipEventDestroy(r.done);
+        if (r.exec) (void)hipGraphExecDestroy(r.exec);
+        if (r.graph) (void)hipGraphDestroy(r.graph);
+        if (r.tab) (void)hipFree(r.tab);
+        return PB_OK;
+    }
+    b->retired.push_back(r);
+    return PB_OK;
+}
+
+// Work lists and descriptor table of the current members, uploaded on the
+// batch stream (ordered after the steps already queued, which keep reading
+// the previous contents); the captured step graph is dropped, to be captured
+// again at the next graph-length step.  No member stream is synchronised.
+int batch_rebuild(pb_batch *b) {
+    const int n = (int)b->doms.size();
+    std::vector<PbTile> tf, tt;
+    std::vector<PbDesc *> ptrs(n);
+    int prec = b->prec, fvar = b->fvar, tvar = b->tvar;
+    if (n > 0) {
+        prec = b->doms[0]->cfg.precision;
+        fvar = b->doms[0]->fvar;
+        std::vector<const pb_config *> cfgs(n);
+        for (int j = 0; j < n; ++j) cfgs[j] = &b->doms[j]->cfg;
+        tvar = launch_thermal_variant(cfgs);
+        int fbx, fby;
+        pb_flow_tile_shape(fvar, &fbx, &fby);
+        // a launch's work-list holds the tiles of the domains that take that
+        // part of the step (frozen-flow domains skip the flow, isothermal ones
+        // the energy equation, as when stepped alone)
+        for (int j = 0; j < n; ++j) {
+            if (!(b->doms[j]->cfg.flags & PB_FROZEN_FLOW))
+                make_tiles(tf, j, b->doms[j]->cfg.nx, b->doms[j]->cfg.ny_fluid, fbx, fby);
+            ptrs[j] = b->doms[j]->ddesc;
+        }
+        thermal_list(tt, cfgs, tvar, b->persistent == 0);
+        if (b->persistent == 0) xcd_order(tf);
+    }
+    const size_t o_tf = align_up((size_t)std::max(n, 1) * sizeof(PbDesc *), kAlign);
+    const size_t o_tt = o_tf + align_up(std::max<size_t>(1, tf.size()) * sizeof(PbTile), kAlign);
+    const size_t total = o_tt + align_up(std::max<size_t>(1, tt.size()) * sizeof(PbTile), kAlign);
+    // the staging copy is rewritten only after the previous upload has read it
+    if (b->upload_pending) {
+        PB_HIP(hipEventSynchronize(b->ev_upload));
+        b->upload_pending = false;
+    }
+    if (total > b->htab_cap) {
+        if (b->htab) PB_HIP(hipHostFree(b->htab));
+        b->htab = nullptr;
+        b->htab_cap = 0;
+        if (hipHostMalloc((void **)&b->htab, 2 * total, hipHostMallocDefault) != hipSuccess)
+            return fail(PB_ENOMEM, "pinned staging of %zu bytes failed", 2 * total);
+        b->htab_cap = 2 * total;
+    }
+    char *old_tab = nullptr;
+    if (total > b->tab_cap) {
+        char *t = nullptr;
+        if (hipMalloc((void **)&t, 2 * total) != hipSuccess)
+            return fail(PB_ENOMEM, "batch tables allocation of %zu bytes failed", 2 * total);
+        old_tab = b->dtab;
+        b->dtab = t;
+        b->tab_cap = 2 * total;
+    }
+    memcpy(b->htab, ptrs.data(), (size_t)n * sizeof(PbDesc *));
+    memcpy(b->htab + o_tf, tf.data(), tf.size() * sizeof(PbTile));
+    memcpy(b->htab + o_tt, tt.data(), tt.size() * sizeof(PbTile));
+    // what was captured or queued before reads the previous tables (and
+    // buffer): retire them behind that work
+    int rc = batch_retire(b, old_tab);
+    if (rc) return rc;
+    PB_HIP(hipMemcpyAsync(b->dtab, b->htab, total, hipMemcpyHostToDevice, b->stream));
+    PB_HIP(hipEventRecord(b->ev_upload, b->stream));
+    b->upload_pending = true;
+    b->dptrs = (PbDesc **)b->dtab;
+    b->dtiles_flow = (PbTile *)(b->dtab + o_tf);
+    b->dtiles_th = (PbTile *)(b->dtab + o_tt);
+    b->prec = prec;
+    b->fvar = fvar;
+    b->tvar = tvar;
+    b->nt_flow = (int)tf.size();
+    b->nt_th = (int)tt.size();
+    b->grid_flow = b->persistent > 0 ? std::min(b->nt_flow, b->persistent) : b->nt_flow;
+    b->grid_th = b->persistent > 0 ? std::min(b->nt_th, b->persistent) : b->nt_th;
+    b->dom_streams.clear();
+    for (pb_domain *d : b->doms)
+        if (std::find(b->dom_streams.begin(), b->dom_streams.end(), d->stream) == b->dom_streams.end())
+            b->dom_streams.push_back(d->stream);
+    batch_reap(b, false);
+    return PB_OK;
+}
+
+int check_member(const pb_batch *b, const pb_domain *d) {
+    if (!d) return fail(PB_EINVAL, "domain is NULL");
+    if (!d->fields_set) return fail(PB_ESTATE, "domain has no fields");
+    if (!b->doms.empty() && d->cfg.precision != b->doms[0]->cfg.precision)
+        return fail(PB_EINVAL, "mixed precisions in one batch");
+    if (std::find(b->doms.begin(), b->doms.end(), d) != b->doms.end()) return fail(PB_EINVAL, "domain listed twice");
+    return PB_OK;
+}
+
+}  // namespace
+
 int pb_batch_create(pb_domain *const *doms, int32_t n, int32_t steps_per_graph, int32_t persistent_blocks, void *stream,
                     pb_batch **out) {
     if (!out) return fail(PB_EINVAL, "out is NULL");
@@ -784,77 +965,68 @@ int pb_batch_create(pb_domain *const *doms, int32_t n, int32_t steps_per_graph, 
     if (!doms || n < 1) return fail(PB_EINVAL, "need at least one domain");
     if (steps_per_graph < 0 || (steps_per_graph & 1)) return fail(PB_EINVAL, "steps_per_graph must be even and >= 0");
     if (persistent_blocks < 0) return fail(PB_EINVAL, "persistent_blocks must be >= 0");
-    const int prec = doms[0]->cfg.precision;
-    for (int j = 0; j < n; ++j) {
-        if (!doms[j]) return fail(PB_EINVAL, "domain %d is NULL", j);
-        if (!doms[j]->fields_set) return fail(PB_ESTATE, "domain %d has no fields", j);
-        if (doms[j]->cfg.precision != prec) return fail(PB_EINVAL, "mixed precisions in one batch");
-        for (int i = 0; i < j; ++i)
-            if (doms[i] == doms[j]) return fail(PB_EINVAL, "domain listed twice");
-    }
     pb_batch *b = new (std::nothrow) pb_batch();
     if (!b) return fail(PB_ENOMEM, "host allocation failed");
-    b->doms.assign(doms, doms + n);
-    b->stream = (hipStream_t)stream;
-    for (int j = 0; j < n; ++j)
-        if (std::find(b->dom_streams.begin(), b->dom_streams.end(), doms[j]->stream) == b->dom_streams.end())
-            b->dom_streams.push_back(doms[j]->stream);
-    b->prec = prec;
-    b->fvar = doms[0]->fvar;
-    std::vector<const pb_config *> cfgs(n);
-    for (int j = 0; j < n; ++j) cfgs[j] = &doms[j]->cfg;
-    b->tvar = launch_thermal_variant(cfgs);
-    b->spg = steps_per_graph;
-    std::vector<PbTile> tf, tt;
-    std::vector<PbDesc *> ptrs(n);
-    int fbx, fby;
-    pb_flow_tile_shape(b->fvar, &fbx, &fby);
-    // a launch's work-list holds the tiles of the domains that take that part
-    // of the step (frozen-flow domains skip the flow, isothermal ones the
-    // energy equation, as when stepped alone)
     for (int j = 0; j < n; ++j) {
-        if (!(doms[j]->cfg.flags & PB_FROZEN_FLOW)) make_tiles(tf, j, doms[j]->cfg.nx, doms[j]->cfg.ny_fluid, fbx, fby);
-        ptrs[j] = doms[j]->ddesc;
+        int rc = check_member(b, doms[j]);
+        if (rc) {
+            delete b;
+            return rc;
+        }
+        b->doms.push_back(doms[j]);
     }
-    thermal_list(tt, cfgs, b->tvar, persistent_blocks == 0);
-    b->nt_flow = (int)tf.size();
-    b->nt_th = (int)tt.size();
-    b->grid_flow = persistent_blocks > 0 ? std::min(b->nt_flow, (int)persistent_blocks) : b->nt_flow;
-    b->grid_th = persistent_blocks > 0 ? std::min(b->nt_th, (int)persistent_blocks) : b->nt_th;
-    if (persistent_blocks == 0) xcd_order(tf);
-    auto bad = [&](int code) {
-        if (b->ev_batch) (void)hipEventDestroy(b->ev_batch);
-        if (b->ev_dom) (void)hipEventDestroy(b->ev_dom);
-        if (b->owns_stream) (void)hipStreamDestroy(b->stream);
-        if (b->dptrs) (void)hipFree(b->dptrs);
-        if (b->dtiles_flow) (void)hipFree(b->dtiles_flow);
-        if (b->dtiles_th) (void)hipFree(b->dtiles_th);
-        delete b;
-        return code;
-    };
+    b->stream = (hipStream_t)stream;
+    b->spg = steps_per_graph;
+    b->persistent = persistent_blocks;
     // graphs cannot be captured on the legacy null stream: use an own stream,
     // ordered against the members' streams with events in pb_batch_step
+    int rc = PB_OK;
     if (!b->stream) {
         if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
-            return bad(fail(PB_EDEVICE, "stream creation failed"));
-        b->owns_stream = true;
+            rc = fail(PB_EDEVICE, "stream creation failed");
+        else
+            b->owns_stream = true;
     }
-    if (hipEventCreateWithFlags(&b->ev_batch, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&b->ev_dom, hipEventDisableTiming) != hipSuccess)
-        return bad(fail(PB_EDEVICE, "event creation failed"));
-    if (hipMalloc((void **)&b->dptrs, n * sizeof(void *)) != hipSuccess ||
-        hipMalloc((void **)&b->dtiles_flow, std::max<size_t>(1, tf.size()) * sizeof(PbTile)) != hipSuccess ||
-        hipMalloc((void **)&b->dtiles_th, std::max<size_t>(1, tt.size()) * sizeof(PbTile)) != hipSuccess)
-        return bad(fail(PB_ENOMEM, "batch tables allocation failed"));
-    for (int j = 0; j < n; ++j)
-        if (hipStreamSynchronize(doms[j]->stream) != hipSuccess) return bad(fail(PB_EDEVICE, "sync failed"));
-    if (hipMemcpy(b->dptrs, ptrs.data(), n * sizeof(void *), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b->dtiles_flow, tf.data(), tf.size() * sizeof(PbTile), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b->dtiles_th, tt.data(), tt.size() * sizeof(PbTile), hipMemcpyHostToDevice) != hipSuccess)
-        return bad(fail(PB_EDEVICE, "batch tables upload failed"));
+    if (!rc && (hipEventCreateWithFlags(&b->ev_batch, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&b->ev_dom, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&b->ev_upload, hipEventDisableTiming) != hipSuccess))
+        rc = fail(PB_EDEVICE, "event creation failed");
+    if (!rc) rc = batch_rebuild(b);
+    if (rc) {
+        pb_batch_destroy(b);
+        return rc;
+    }
     *out = b;
     return PB_OK;
 }
+
+int pb_batch_add(pb_batch *b, pb_domain *d) {
+    if (!b) return fail(PB_EINVAL, "batch is NULL");
+    int rc = check_member(b, d);
+    if (rc) return rc;
+    b->doms.push_back(d);
+    if ((rc = batch_rebuild(b))) {
+        b->doms.pop_back();
+        return rc;
+    }
+    return PB_OK;
+}
+
+int pb_batch_remove(pb_batch *b, pb_domain *d) {
+    if (!b) return fail(PB_EINVAL, "batch is NULL");
+    auto it = std::find(b->doms.begin(), b->doms.end(), d);
+    if (!d || it == b->doms.end()) return fail(PB_EINVAL, "domain is not a member of the batch");
+    const size_t at = (size_t)(it - b->doms.begin());
+    b->doms.erase(it);
+    int rc = batch_rebuild(b);
+    if (rc) {
+        b->doms.insert(b->doms.begin() + at, d);
+        return rc;
+    }
+    return PB_OK;
+}
+
+int32_t pb_batch_size(const pb_batch *b) { return b ? (int32_t)b->doms.size() : -1; }
 
 // Which of the next nsteps steps (step k ends at t + k + 1) some member
 // samples for the heat flux.  The flux kernel checks each domain's window and
@@ -894,6 +1066,7 @@ static int batch_enqueue(pb_batch *b, int nsteps, const std::vector<char> &flux)
 int pb_batch_step(pb_batch *b, int64_t n) {
     if (!b) return fail(PB_EINVAL, "batch is NULL");
     if (n < 0) return fail(PB_EINVAL, "n must be >= 0");
+    if (b->doms.empty() || n == 0) return PB_OK;
     int rc;
     // the batch stream starts after the work already queued on member streams
     for (hipStream_t s : b->dom_streams) {
@@ -906,18 +1079,17 @@ int pb_batch_step(pb_batch *b, int64_t n) {
             // a member's flux window or phase changed since the capture: capture again
             const std::vector<char> flux = batch_flux_steps(b, b->spg, true);
             if (b->gexec && flux != b->graph_flux) {
-                PB_HIP(hipStreamSynchronize(b->stream));
-                PB_HIP(hipGraphExecDestroy(b->gexec));
-                PB_HIP(hipGraphDestroy(b->graph));
-                b->gexec = nullptr;
-                b->graph = nullptr;
+                if ((rc = batch_retire(b, nullptr))) return rc;
             }
             if (!b->gexec) {
                 PB_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
                 rc = batch_enqueue(b, b->spg, flux);
                 hipGraph_t g = nullptr;
                 hipError_t e = hipStreamEndCapture(b->stream, &g);
-                if (rc) return rc;
+                if (rc) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return rc;
+                }
                 if (e != hipSuccess) return fail(PB_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
                 b->graph = g;
                 b->graph_flux = flux;
@@ -952,15 +1124,16 @@ int pb_batch_step(pb_batch *b, int64_t n) {
 
 void pb_batch_destroy(pb_batch *b) {
     if (!b) return;
-    (void)hipStreamSynchronize(b->stream);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    batch_reap(b, true);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->ev_batch) (void)hipEventDestroy(b->ev_batch);
     if (b->ev_dom) (void)hipEventDestroy(b->ev_dom);
+    if (b->ev_upload) (void)hipEventDestroy(b->ev_upload);
     if (b->owns_stream) (void)hipStreamDestroy(b->stream);
-    (void)hipFree(b->dptrs);
-    (void)hipFree(b->dtiles_flow);
-    (void)hipFree(b->dtiles_th);
+    if (b->dtab) (void)hipFree(b->dtab);
+    if (b->htab) (void)hipHostFree(b->htab);
     delete b;
 }
 

@@ -21,7 +21,7 @@ EXPORTED = [
     "pb_domain_bytes", "pb_thermal_strip_rows", "pb_thermal_work_list", "pb_create_domain", "pb_destroy_domain", "pb_set_bc", "pb_set_fields", "pb_set_fields_full",
     "pb_step", "pb_sync", "pb_read_fields", "pb_flux_window", "pb_heat_flux", "pb_profile_steps", "pb_time",
     "pb_rho_bar",
-    "pb_batch_create", "pb_batch_step", "pb_batch_destroy", "pb_eos_critical_temperature", "pb_eos_coexistence",
+    "pb_batch_create", "pb_batch_step", "pb_batch_destroy", "pb_batch_add", "pb_batch_remove", "pb_batch_size", "pb_eos_critical_temperature", "pb_eos_coexistence",
     "pb_eos_psi", "pb_eos_latent_heat", "pb_last_error", "pb_version",
 ]
 
@@ -99,6 +99,9 @@ def _load():
         "pb_batch_create": ([C.POINTER(vp), i32, i32, i32, vp, C.POINTER(vp)], C.c_int),
         "pb_batch_step": ([vp, i64], C.c_int),
         "pb_batch_destroy": ([vp], None),
+        "pb_batch_add": ([vp, vp], C.c_int),
+        "pb_batch_remove": ([vp, vp], C.c_int),
+        "pb_batch_size": ([vp], i32),
         "pb_eos_critical_temperature": ([C.c_double, C.c_double, C.c_double, dp], C.c_int),
         "pb_eos_coexistence": ([C.c_double] * 6 + [dp, dp], C.c_int),
         "pb_eos_psi": ([C.c_double] * 8 + [dp], C.c_int),
@@ -305,6 +308,19 @@ class Batch:
 
     def step(self, n):
         _check(lib.pb_batch_step(self._h, int(n)))
+
+    def add(self, domain):
+        """Add a domain between steps (pb_batch_add)."""
+        _check(lib.pb_batch_add(self._h, domain.handle))
+        self.domains.append(domain)
+
+    def remove(self, domain):
+        """Take a domain out between steps (pb_batch_remove)."""
+        _check(lib.pb_batch_remove(self._h, domain.handle))
+        self.domains = [d for d in self.domains if d is not domain]
+
+    def __len__(self):
+        return int(lib.pb_batch_size(self._h))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -6,7 +6,8 @@ second half of the run, reported with its Jakob number (Eq. 37).
 
 Scheduling.  Resident jobs keep their whole state in HBM and are stepped in
 lock-step by one shared launch per kernel (pb_batch), replayed from a
-captured HIP graph when a chunk has the full graph length.  Work proceeds in
+captured HIP graph when a chunk has the full graph length.  Jobs join and
+leave that one batch in place (pb_batch_add / pb_batch_remove).  Work proceeds in
 chunks: each chunk ends exactly when the first resident job finishes (or
 after `chunk_steps`), so every job runs exactly its own number of steps.
 While a chunk runs on the GPU the host admits waiting jobs whose device
@@ -66,6 +67,7 @@ class ServerStats:
     admitted: int = 0
     retired: int = 0
     max_resident: int = 0
+    batch_changes: int = 0        # pb_batch_add / pb_batch_remove calls
     node_updates: float = 0.0
     busy_s: float = 0.0
     occupancy: list = field(default_factory=list)
@@ -175,12 +177,17 @@ class Server:
         n = min([self.chunk_steps] + [j.spec.steps - j.done_steps for j in self.resident])
         t0 = self.clock()
         if self.batching:
-            members = tuple(j.job_id for j in self.resident)
-            if members != self._batch_members:
-                if self._batch is not None:
-                    self._batch.close()
+            if self._batch is None:
                 self._batch = pb.Batch([j.dom for j in self.resident], steps_per_graph=self.graph_steps)
-                self._batch_members = members
+                self._batch_members = {j.job_id for j in self.resident}
+            else:
+                # admitted jobs join the running batch (pb_batch_add: the work
+                # lists change in place, no member waits)
+                for j in self.resident:
+                    if j.job_id not in self._batch_members:
+                        self._batch.add(j.dom)
+                        self._batch_members.add(j.job_id)
+                        self.stats.batch_changes += 1
             self._batch.step(n)
             if self.graph_steps and n >= self.graph_steps:
                 self.stats.graph_chunks += 1
@@ -233,9 +240,12 @@ class Server:
                       Ja=j.spec.overrides.get("Cv", presets.W.BASE_PARAMS["Cv"]) * j.spec.superheat * d.Tc / self.h_fg,
                       steps=j.done_steps, arrival=j.arrival, start=j.start, finish=now, error=error)
         self.results[j.job_id] = r
-        if self._batch is not None and j.job_id in (self._batch_members or ()):
-            self._batch.close()
-            self._batch, self._batch_members = None, None
+        if self._batch is not None and j.job_id in self._batch_members:
+            # it leaves the batch; the work already queued for it has run
+            # (the chunk was synchronised above), so it can go at once
+            self._batch.remove(j.dom)
+            self._batch_members.discard(j.job_id)
+            self.stats.batch_changes += 1
         j.dom.close()
         j.dom = None
         j.stream = None

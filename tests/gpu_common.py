@@ -68,4 +68,8 @@ def compare(g, o, keys=("rho", "ux", "uy", "T", "f")):
             out[k] = float(np.max(np.abs(g[k] - o[k])) / uscale)
         else:
             out[k] = rel_err(g[k], o[k])
+    # the per-component form (each velocity component over its own maximum),
+    # printed beside the bar for the record
+    own = {k: rel_err(g[k], o[k]) for k in ("ux", "uy") if k in keys}
+    print("per-component velocity errors", {k: f"{v:.2e}" for k, v in own.items()}, flush=True)
     return out

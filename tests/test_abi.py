@@ -8,7 +8,7 @@ import pytest
 
 from conftest import ROOT
 from helpers import derived
-import workloads as W
+from paper_1911_10747_amd import workloads as W
 
 HEADER = os.path.join(ROOT, "include", "poolboil.h")
 
@@ -71,6 +71,13 @@ def test_invalid_configs_rejected_without_gpu():
             pb.domain_bytes(cfg)
         assert ei.value.code == pb.PB_EINVAL
     assert pb.domain_bytes(pb.make_config(**base)) > 0
+    # 32-bit element offsets: nine population planes of 14600 x 32768 nodes
+    # pass 2^32 (about 50 GB in FP32, so the memory itself would fit)
+    big = pb.make_config(**dict(base, nx=32768, ny_fluid=14600, ny_solid=64))
+    with pytest.raises(pb.PbError) as ei:
+        pb.domain_bytes(big)
+    assert ei.value.code == pb.PB_EINVAL and "32-bit" in str(ei.value)
+    assert pb.domain_bytes(pb.make_config(**dict(base, nx=32768, ny_fluid=14500, ny_solid=64))) > 0
 
 
 def test_energy_strip_height_by_domain_size():

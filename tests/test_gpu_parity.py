@@ -11,8 +11,8 @@ checkpoint/resume in FP64).
 import numpy as np
 import pytest
 
-import workloads as W
-from gpu_common import compare, gpu_domain, oracle_domain, pb_config, run_pair
+from paper_1911_10747_amd import workloads as W
+from gpu_common import compare, gpu_domain, oracle_domain, pb_config, rel_err, run_pair
 from helpers import params, pool_case
 
 pytestmark = pytest.mark.gpu
@@ -23,6 +23,26 @@ TOL = {0: 1e-11, 1: 2e-5}
 
 def _report(name, errs):
     print(name, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+
+
+@pytest.mark.parametrize("flag", ["varpi_fm_only", "sbar2_plus"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_printed_readings_of_eq9(flag, precision):
+    """The two printed forms of Eq. 9 that this build reads otherwise, as
+    flags on both sides: the varpi term with F_m of Eq. 11 alone
+    (PB_VARPI_FM_ONLY) and with a + sign in row 2 (PB_SBAR2_PLUS).  The
+    100x100 + 100x10 pool for 200 steps against the oracle with the same flag,
+    and the flag changes the result (so it is in effect on both sides)."""
+    P, d, bc, rho, T = pool_case(100, 100, 10, superheat=0.1, n_spots=4, seed=0, y0=40, **{flag: 1})
+    g, o = run_pair(P, bc, rho, T, steps=200, precision=precision, window=(50, 201, 10))
+    errs = compare(g, o)
+    _report(f"{flag} prec={precision}", errs)
+    assert all(v <= TOL[precision] for v in errs.values()), errs
+    assert g["flux"]["q_bottom_mean"] == pytest.approx(o["flux"]["q_bottom_mean"], rel=TOL[precision] * 10)
+    P0 = dict(P, **{flag: 0})
+    o0 = oracle_domain(P0, bc, rho, T)
+    o0.step(200)
+    assert rel_err(o0.read()["f"], o["f"]) > 1e-6
 
 
 @pytest.mark.parametrize("tile", [(0, 0), (64, 4)])
@@ -291,6 +311,72 @@ def test_batch_of_auto_strip_domains_matches_alone(precision):
     batch.close()
     for g in doms:
         g.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_membership_changes_bit_identical(precision):
+    """Domains join and leave a running batch between steps (pb_batch_add,
+    pb_batch_remove), each at a different time of its own, with graph
+    replays and eager steps before and after every change, down to an empty
+    batch: each domain equals the same domain stepped alone for its own number
+    of steps, bit for bit, heat flux included.  A removed domain is read and
+    destroyed right after its removal while the batch goes on."""
+    from paper_1911_10747_amd import poolboil as pb
+    cases = [pool_case(70, 50, 4, superheat=0.08, seed=1), pool_case(33, 20, 3, superheat=0.25, seed=2),
+             pool_case(130, 64, 7, superheat=0.15, seed=3), pool_case(50, 40, 5, superheat=0.2, seed=4)]
+    steps = [50, 91, 71, 28]
+    alone = []
+    for (P, d, bc, rho, T), n in zip(cases, steps):
+        g = gpu_domain(P, bc, rho, T, precision)
+        g.flux_window(10, 1000, 5)
+        g.step(n)
+        g.sync()
+        alone.append((g.read(), g.heat_flux()))
+        g.close()
+    doms = []
+    for P, d, bc, rho, T in cases:
+        g = gpu_domain(P, bc, rho, T, precision)
+        g.flux_window(10, 1000, 5)
+        doms.append(g)
+    A, B, C, D = doms
+    got = {}
+
+    def leave(k, dom):
+        batch.remove(dom)
+        got[k] = (dom.read(), dom.heat_flux(), dom.t)
+        dom.close()
+
+    batch = pb.Batch([A, B], steps_per_graph=10)
+    batch.step(20)                     # two replays
+    batch.add(C)
+    assert len(batch) == 3
+    batch.step(30)                     # captured again, three replays
+    leave(0, A)
+    batch.step(25)                     # two replays and five eager steps
+    batch.add(D)
+    batch.step(16)
+    leave(1, B)
+    leave(2, C)
+    batch.step(12)
+    leave(3, D)
+    assert len(batch) == 0
+    batch.step(5)                      # empty batch: nothing to do
+    batch.close()
+    for k, n in enumerate(steps):
+        r, f, t = got[k]
+        r0, f0 = alone[k]
+        assert t == n, (k, t, n)
+        for key in ("rho", "ux", "uy", "T", "f"):
+            np.testing.assert_array_equal(r[key], r0[key], err_msg=f"domain {k}: {key}")
+        assert f == f0, k
+    with pytest.raises(pb.PbError):
+        dup = gpu_domain(*cases[0][0:1], *cases[0][2:], precision)
+        b2 = pb.Batch([dup], steps_per_graph=0)
+        try:
+            b2.add(dup)
+        finally:
+            b2.close()
+            dup.close()
 
 
 def test_batch_flux_windows_set_between_graph_replays():

@@ -26,10 +26,22 @@ class FakeDomain:
 
 class FakeBatch:
     log = []
+    made = 0
 
     def __init__(self, domains, steps_per_graph=0, persistent_blocks=0, stream=None):
-        self.domains = domains
-        FakeBatch.log.append(len(domains))
+        self.domains = list(domains)
+        FakeBatch.made += 1
+        FakeBatch.log.append(len(self.domains))
+
+    def add(self, dom):
+        assert all(d is not dom for d in self.domains) and not dom.closed
+        self.domains.append(dom)
+        FakeBatch.log.append(len(self.domains))
+
+    def remove(self, dom):
+        assert any(d is dom for d in self.domains) and not dom.closed
+        self.domains = [d for d in self.domains if d is not dom]
+        FakeBatch.log.append(len(self.domains))
 
     def step(self, n):
         for d in self.domains:
@@ -57,6 +69,7 @@ def fake(monkeypatch):
     monkeypatch.setattr(presets, "make_domain", make_domain)
     monkeypatch.setattr(pb, "Batch", FakeBatch)
     FakeBatch.log = []
+    FakeBatch.made = 0
     return made
 
 
@@ -73,6 +86,9 @@ def test_every_job_runs_exactly_its_steps_and_budget_holds(fake):
     assert srv.stats.max_resident == 3
     assert max(FakeBatch.log) <= 3
     assert srv.used == 0
+    # one batch for the whole run: jobs joined and left it in place
+    assert FakeBatch.made == 1
+    assert srv.stats.batch_changes == (len(specs) - 3) + len(specs)
 
 
 def test_memory_budget_limits_residency(fake):
