@@ -184,6 +184,20 @@ int pb_sync(pb_domain *dom);
  * if f is not NULL, f(t) after streaming.  Any output pointer may be NULL. */
 int pb_read_fields(pb_domain *dom, double *rho, double *ux, double *uy, double *T, double *f);
 
+/* pb_read_fields for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same outputs, bit for bit, but the FP64 read-back staging is a fixed
+ * device array of PB_READ_NOALLOC_MAX_BYTES that every GPU the library runs
+ * on holds for the life of the process, instead of memory allocated on the
+ * first read.  The domain needs 12 * ny_fluid * pitch * 8 bytes of it (pitch =
+ * nx rounded up to 64, so ny_fluid * pitch <= 699050); a larger domain gets
+ * PB_EINVAL before any device work.  No hipMalloc/hipFree is called.  Every
+ * call on a GPU shares that GPU's array, which keeps the last call's
+ * contents: calls that overlap on one GPU (other threads or streams) race.
+ * Synchronous, like pb_read_fields. */
+#define PB_READ_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+int pb_read_fields_noalloc(pb_domain *dom, double *rho, double *ux, double *uy, double *T, double *f);
+
 /* Heat-flux sampling: a sample is taken after every step that ends at a time
  * t with t_a <= t < t_b and (t - t_a) % every == 0.  Resets the accumulators. */
 int pb_flux_window(pb_domain *dom, int64_t t_a, int64_t t_b, int32_t every);

@@ -37,6 +37,7 @@ int fail(int code, const char *fmt, ...) {
     } while (0)
 
 constexpr size_t kAlign = 256;
+static_assert(PB_SCRATCH_BYTES == PB_READ_NOALLOC_MAX_BYTES, "fixed read-back staging size");
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 const double kWh[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
@@ -732,6 +733,26 @@ int pb_read_fields(pb_domain *d, double *rho, double *ux, double *uy, double *T,
     if (!d->rd && hipMalloc((void **)&d->rd, 12 * nf * sizeof(double)) != hipSuccess)
         return fail(PB_ENOMEM, "read staging allocation failed");
     return read_through(d, d->rd, rho, ux, uy, T, f);
+}
+
+int pb_read_fields_noalloc(pb_domain *d, double *rho, double *ux, double *uy, double *T, double *f) {
+    int rc = check_dom(d);
+    if (rc) return rc;
+    if (!d->fields_set) return fail(PB_ESTATE, "pb_set_fields was not called");
+    const size_t need = 12 * (size_t)d->cfg.ny_fluid * d->pitch * sizeof(double);
+    if (need > PB_SCRATCH_BYTES)
+        return fail(PB_EINVAL, "read-back staging of %zu bytes exceeds the fixed %zu bytes (ny_fluid * pitch <= %zu)",
+                    need, (size_t)PB_SCRATCH_BYTES, (size_t)PB_SCRATCH_BYTES / (12 * sizeof(double)));
+    int cur = 0;
+    PB_HIP(hipGetDevice(&cur));
+    if (cur != d->device) PB_HIP(hipSetDevice(d->device));
+    void *stage = nullptr;
+    size_t cap = 0;
+    hipError_t e = pb_scratch_address(&stage, &cap);
+    if (cur != d->device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return fail(PB_EDEVICE, "staging address lookup failed: %s", hipGetErrorString(e));
+    PB_HIP(hipStreamSynchronize(d->stream));
+    return read_through(d, (double *)stage, rho, ux, uy, T, f);
 }
 
 int pb_flux_window(pb_domain *d, int64_t t_a, int64_t t_b, int32_t every) {

@@ -59,6 +59,13 @@ hipError_t pb_launch_flux(int prec, const PbDesc *const *d_descs, int ndom, int 
 hipError_t pb_launch_advance(PbDesc *const *d_descs, int ndom, int nsteps, hipStream_t s);
 hipError_t pb_launch_init(int prec, const PbDesc *d_desc, const double *rho_src, hipStream_t s);
 
+// Fixed read-back staging of pb_read_fields_noalloc: a file-scope device array
+// of PB_SCRATCH_BYTES in pb_kernels.hip, one per GPU for the life of the
+// process.  pb_scratch_address gives its device address on the current device
+// (looked up once per device with hipGetSymbolAddress).
+#define PB_SCRATCH_BYTES ((size_t)64 << 20)
+hipError_t pb_scratch_address(void **ptr, size_t *bytes);
+
 // Tile geometry of the variants (x, y extents of one block's tile).
 void pb_flow_tile_shape(int variant, int *bx, int *by);
 void pb_thermal_tile_shape(int variant, int *bx, int *by);

@@ -24,6 +24,7 @@
 // (so the FP64 rebuild on load is exact up to the rounding of the deviation),
 // and runs the energy equation in FP32 increments over FP64 T (see the FP32
 // sweep below).
+#include <mutex>
 #include <type_traits>
 
 #include "pb_internal.h"
@@ -1262,4 +1263,33 @@ hipError_t pb_launch_init(int prec, const PbDesc *d_desc, const double *rho_src,
     else
         hipLaunchKernelGGL(k_init<float>, dim3(1024), dim3(256), 0, s, d_desc, rho_src);
     return hipGetLastError();
+}
+
+// ------------------------------------------------- fixed read-back staging
+// Staging for pb_read_fields_noalloc: every GPU the library runs on holds one
+// copy of this array for the life of the process, so that call allocates
+// nothing.  Host code never passes the array's name to a kernel (in host code
+// it is a stand-in, not a device address): it uses the address that
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device.
+static __device__ __align__(256) double scratch[PB_SCRATCH_BYTES / sizeof(double)];
+
+hipError_t pb_scratch_address(void **ptr, size_t *bytes) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    *bytes = PB_SCRATCH_BYTES;
+    return hipSuccess;
 }

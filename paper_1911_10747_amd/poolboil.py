@@ -19,7 +19,7 @@ PB_PERIODIC_Y, PB_ISOTHERMAL, PB_FROZEN_FLOW, PB_SBAR2_PLUS, PB_VARPI_FM_ONLY = 
 
 EXPORTED = [
     "pb_domain_bytes", "pb_thermal_strip_rows", "pb_thermal_work_list", "pb_create_domain", "pb_destroy_domain", "pb_set_bc", "pb_set_fields", "pb_set_fields_full",
-    "pb_step", "pb_sync", "pb_read_fields", "pb_flux_window", "pb_heat_flux", "pb_profile_steps", "pb_time",
+    "pb_step", "pb_sync", "pb_read_fields", "pb_read_fields_noalloc", "pb_flux_window", "pb_heat_flux", "pb_profile_steps", "pb_time",
     "pb_rho_bar",
     "pb_batch_create", "pb_batch_step", "pb_batch_destroy", "pb_batch_add", "pb_batch_remove", "pb_batch_size", "pb_eos_critical_temperature", "pb_eos_coexistence",
     "pb_eos_psi", "pb_eos_latent_heat", "pb_last_error", "pb_version",
@@ -91,6 +91,7 @@ def _load():
         "pb_step": ([vp, i64], C.c_int),
         "pb_sync": ([vp], C.c_int),
         "pb_read_fields": ([vp, dp, dp, dp, dp, dp], C.c_int),
+        "pb_read_fields_noalloc": ([vp, dp, dp, dp, dp, dp], C.c_int),
         "pb_flux_window": ([vp, i64, i64, i32], C.c_int),
         "pb_heat_flux": ([vp, C.POINTER(Flux)], C.c_int),
         "pb_profile_steps": ([vp, i64, dp], C.c_int),
@@ -258,12 +259,15 @@ class Domain:
     def sync(self):
         _check(lib.pb_sync(self._h))
 
-    def read(self, with_f=True):
+    def read(self, with_f=True, noalloc=False):
+        """rho, ux, uy, T (and f) at the current time; noalloc: through the
+        fixed per-GPU staging (pb_read_fields_noalloc)."""
         nf = (self.nyf, self.nx)
         rho, ux, uy = np.empty(nf), np.empty(nf), np.empty(nf)
         T = np.empty((self.nr, self.nx))
         f = np.empty((9,) + nf) if with_f else None
-        _check(lib.pb_read_fields(self._h, _dptr(rho), _dptr(ux), _dptr(uy), _dptr(T), _dptr(f)))
+        fn = lib.pb_read_fields_noalloc if noalloc else lib.pb_read_fields
+        _check(fn(self._h, _dptr(rho), _dptr(ux), _dptr(uy), _dptr(T), _dptr(f)))
         out = dict(rho=rho, ux=ux, uy=uy, T=T)
         if with_f:
             out["f"] = f
