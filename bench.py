@@ -134,31 +134,99 @@ def per_kernel(nx, nyf, nys, prec, prof, rec):
     return out
 
 
-def cpu_baseline(nx, nyf, nys, steps):
-    """The FP64 oracle, as it stands, on `steps` steps of the same workload
-    (serial C, one core)."""
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
+def _oracle_pool_domain(nx, nyf, nys, superheat, n_spots, seed):
+    """The oracle set up on the standard pool-boiling start (liquid layer at
+    the Maxwell density below 40% of the height, heater-bottom superheat with
+    +2% hot spots, wall adhesion -0.7 psi_L, top wall -psi_V), constants from
+    the oracle's own thermodynamics."""
     from paper_1911_10747_amd import workloads as W
     from oracle import eos, orc
+    import numpy as np
     P = dict(W.BASE_PARAMS)
     Tc = eos.critical_temperature(P["a"], P["b"], P["R"])
     Ts = W.T_SAT_OVER_TC * Tc
     rl, rv, _ = eos.maxwell(Ts, P["a"], P["b"], P["R"], P["omega"], Tc)
-    import numpy as np
     P.update(nx=nx, nyf=nyf, nys=nys, Tc=Tc, rho_L=rl, rho_V=rv, rho_S=W.RHO_S_OVER_RHO_L * rl,
              g=W.gravity_for_height(nyf))
     dom = orc.Domain(**P)
-    Tb = W.spot_Tb(nx, Ts + 0.1 * Tc, max(1, nx // 64), 0)
+    Tb = W.spot_Tb(nx, Ts + superheat * Tc, n_spots, seed)
     gam = np.full(nx, -0.7 * eos.psi(rl, Ts, P["a"], P["b"], P["R"], P["omega"], Tc))
     gtop = np.full(nx, -eos.psi(rv, Ts, P["a"], P["b"], P["R"], P["omega"], Tc))
     dom.set_bc(Ts, Tb, gamma_bot=gam, gamma_top=gtop)
     dom.set_fields(W.layered_rho(nx, nyf, int(round(0.4 * nyf)), rl, rv), W.thermal_init(nx, nys, nyf, Ts, Tb))
+    return dom
+
+
+def cpu_baseline(nx, nyf, nys, steps):
+    """The FP64 oracle, as it stands, on `steps` steps of the same workload
+    (serial C, one core)."""
+    dom = _oracle_pool_domain(nx, nyf, nys, 0.1, max(1, nx // 64), 0)
     t0 = time.perf_counter()
     dom.step(steps)
     dt = time.perf_counter() - t0
     return dict(value=nx * nyf * steps / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
                 sample=f"{steps} steps of the full {nx}x{nyf}+{nys} domain, serial FP64 C oracle, one core, "
                        f"{dt:.1f} s")
+
+
+def _oracle_job_step_time(job):
+    """Worker of cpu_jobs_baseline: seconds per oracle step of one job,
+    measured over its window of steps (in a process of its own, so the
+    jobs' windows run concurrently, one per core)."""
+    dom = _oracle_pool_domain(job["nx"], job["nyf"], job["nys"], job["superheat"],
+                              max(1, job["nx"] // 64), job["seed"])
+    dom.step(2)
+    t0 = time.perf_counter()
+    dom.step(job["window"])
+    return (time.perf_counter() - t0) / job["window"]
+
+
+def _fifo_schedule(durations, arrivals, cores):
+    """Finish times of jobs served first come first served on `cores`
+    single-thread workers."""
+    import heapq
+    free = [0.0] * cores
+    heapq.heapify(free)
+    finish = []
+    for a, dur in sorted(zip(arrivals, durations), key=lambda p: p[0]):
+        start = max(a, heapq.heappop(free))
+        heapq.heappush(free, start + dur)
+        finish.append((a, start + dur))
+    return finish
+
+
+def cpu_jobs_baseline(jobs, window, cores, rates=()):
+    """The oracle on a boiling-curve job mix, one single-thread oracle
+    process per host core: every job's step time is measured on its own
+    domain over `window` steps, all jobs' windows running concurrently on
+    `cores` processes, and scaled to the job's full number of steps; the
+    jobs are then served first come first served on `cores` workers, all
+    submitted at once (jobs/hour, p50/p99 latency) and, for each rate in
+    `rates` (jobs/s), on the seeded arrival trace replayed at that rate."""
+    import multiprocessing as mp
+    import numpy as np
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        per_step = pool.map(_oracle_job_step_time, [dict(j, window=window) for j in jobs], chunksize=1)
+    wall = time.perf_counter() - t0
+    dur = [ps * j["steps"] for ps, j in zip(per_step, jobs)]
+
+    def served(arrivals):
+        fin = _fifo_schedule(dur, arrivals, cores)
+        lat = np.array([f - a for a, f in fin])
+        span = max(f for _, f in fin) - min(arrivals)
+        return dict(jobs_per_hour=round(len(jobs) / span * 3600.0, 3), p50_latency_s=round(float(np.percentile(lat, 50)), 1),
+                    p99_latency_s=round(float(np.percentile(lat, 99)), 1))
+
+    out = dict(cores=cores, kind="oracle", all_at_once=served([0.0] * len(jobs)),
+               mlups_per_core=round(float(np.mean([j["nx"] * j["nyf"] / ps for ps, j in zip(per_step, jobs)])) / 1e6, 3),
+               sample=f"each job's oracle step time measured over {window} steps of its own domain, the {len(jobs)} "
+                      f"jobs' windows run concurrently on {cores} single-thread processes ({wall:.1f} s), scaled to "
+                      f"the job's full steps")
+    if rates and all("arrival" in j for j in jobs):
+        base = [j["arrival"] for j in jobs]
+        out["trace"] = [dict(rate_jobs_per_s=r, **served([a / r for a in base])) for r in rates]
+    return out
 
 
 def small_configs(log):
@@ -294,7 +362,9 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="roofline", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-job-window", type=int, default=10,
+                    help="oracle steps timed per job for the CPU jobs/hour baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default="0x0")
     ap.add_argument("--thermal-tile", type=int, default=0)
@@ -379,6 +449,10 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
+            # the same bytes over the wall-clock time per step (launch gaps and
+            # the heat-flux samples included)
+            "achieved_wall": round(alg / (ms_step * 1e-3) / 1e9, 1),
+            "frac_wall": round(alg / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "traffic": traffic,
             "traffic_gbs": round(traffic / (kern_ms * 1e-3) / 1e9, 1) if traffic else None,
             "traffic_frac": round(traffic / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
@@ -398,10 +472,23 @@ def main():
         if "small_configs" in out:
             out["cpu_baseline"]["pool_100x100+10"] = cpu_baseline(100, 100, 10, 200)
         if "serving" in out:
-            # the same boiling-curve jobs on the oracle, one job per host core
-            bc = out["serving"]["boiling_curve"]
-            bc["cpu_oracle_jobs_per_hour_per_core"] = round(
-                out["cpu_baseline"]["value"] * 1e6 * 3600.0 / bc["mean_job_fluid_node_updates"], 3)
+            # the same job mixes on the oracle, one single-thread process per
+            # host core (at most 16: the host's share for one GPU)
+            from paper_1911_10747_amd import workloads as W
+            cores = max(1, min(16, len(os.sched_getaffinity(0))))
+            sv = out["serving"]
+            print(f"bench: oracle jobs/hour on {cores} cores", file=sys.stderr, flush=True)
+            curve = cpu_jobs_baseline(W.batch_jobs(seed=0, n=32, steps=20000), args.cpu_job_window, cores)
+            rates = [lv["rate_jobs_per_s"] for lv in sv["poisson_stream"]["levels"]]
+            stream = cpu_jobs_baseline(W.job_stream(seed=0, n=48, rate_per_s=1.0), args.cpu_job_window, cores,
+                                       rates=rates)
+            out["cpu_baseline"]["boiling_curve_jobs"] = curve
+            out["cpu_baseline"]["poisson_stream_jobs"] = stream
+            bc = sv["boiling_curve"]
+            bc["cpu_oracle_jobs_per_hour"] = curve["all_at_once"]["jobs_per_hour"]
+            bc["cpu_oracle_cores"] = cores
+            bc["speedup_vs_cpu_oracle"] = round(bc["fp32_batched"]["jobs_per_hour"] /
+                                                curve["all_at_once"]["jobs_per_hour"], 1)
     print(json.dumps(out), flush=True)
 
 
