@@ -79,6 +79,63 @@ def load_profile(workload):
     return rec
 
 
+def _pmc_per_dispatch(path, counter):
+    """Per-kernel lists of one counter's value per dispatch from a rocprofv3
+    --pmc CSV (rows of one dispatch summed)."""
+    import csv
+    import re
+    per = {}
+    with open(path, newline="") as fh:
+        for row in csv.DictReader(fh):
+            if row.get("Counter_Name") != counter:
+                continue
+            name = row["Kernel_Name"]
+            m = re.search(r"(k_\w+<[^>]*>|__amd_rocclr_\w+)", name)
+            key = m.group(1) if m else name
+            disp = row.get("Dispatch_Id") or row.get("Correlation_Id")
+            per.setdefault(key, {}).setdefault(disp, 0.0)
+            per[key][disp] += float(row["Counter_Value"])
+    return {k: list(v.values()) for k, v in per.items()}
+
+
+def write_traffic_profile(fetch_csv, write_csv, valu_csv, copy_bytes, out, workload, command):
+    """Summarise three rocprofv3 --pmc runs of the same command (FETCH_SIZE,
+    WRITE_SIZE, SQ_INSTS_VALU; KiB / instructions per dispatch) into the
+    per-launch HBM bytes and VALU instructions that load_profile reads.  The
+    byte counters are scaled by what they read for the device-to-device copy
+    of copy_bytes the command starts with (the runtime's copy kernel), so
+    that the copy reads and writes exactly copy_bytes."""
+    import numpy as np
+    fetch = _pmc_per_dispatch(fetch_csv, "FETCH_SIZE")
+    write = _pmc_per_dispatch(write_csv, "WRITE_SIZE")
+    valu = _pmc_per_dispatch(valu_csv, "SQ_INSTS_VALU")
+    copy = [k for k in fetch if "copyBuffer" in k]
+    if not copy:
+        raise SystemExit("no copy kernel in the FETCH_SIZE run: run the command with --copy-calibration")
+    fk = max(max(fetch[k]) for k in copy)
+    wk = max(max(write[k]) for k in copy if k in write)
+    cal = dict(copy_bytes=copy_bytes, fetch_kib=fk, write_kib=wk, fetch_factor=copy_bytes / (fk * 1024.0),
+               write_factor=copy_bytes / (wk * 1024.0))
+    rec = dict(calibration=cal)
+    total = 0
+    for key in sorted(fetch):
+        if not key.startswith(("k_flow", "k_thermal")):
+            continue
+        rd = float(np.mean(fetch[key])) * 1024.0 * cal["fetch_factor"]
+        wr = float(np.mean(write.get(key, [0.0]))) * 1024.0 * cal["write_factor"]
+        rec[key] = dict(read_bytes=int(rd), write_bytes=int(wr), total_bytes=int(rd + wr), launches=len(fetch[key]),
+                        valu_insts=int(np.mean(valu[key])) if key in valu else None)
+        total += int(rd + wr)
+    rec.update(roofline_bytes_per_step=total, source_sha256=source_sha256(), workload=workload, command=command,
+               method="per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) averaged over each kernel's launches and scaled by "
+                      "true/measured for the device-to-device copy of the same run; valu_insts: SQ_INSTS_VALU "
+                      "(wavefront VALU instructions) per dispatch, averaged; source_sha256: SHA-256 of "
+                      "pb_kernels.hip followed by pb_api.cpp")
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec
+
+
 def kernel_record(rec, prefix):
     """The profile entry of the kernel whose name starts with prefix."""
     if rec is None:
@@ -372,7 +429,19 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the boiling-curve / job-stream legs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (reference for HBM counters)")
+    ap.add_argument("--traffic-profile", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "VALU_CSV"),
+                    help="summarise three rocprofv3 --pmc runs of this command into profiles/ (no GPU work)")
     args = ap.parse_args()
+    if args.traffic_profile:
+        out = os.path.join(ROOT, "profiles", TRAFFIC_FILES[args.workload])
+        cmd = ("cd /tmp && timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out> -o fetch -- "
+               "python3 <repo>/bench.py --no-tune --tile 64x8 --thermal-tile 0 --steps 10 --warmup 2 "
+               "--no-cpu-baseline --no-serving --copy-calibration 1024   (and the same with --pmc WRITE_SIZE and "
+               "--pmc SQ_INSTS_VALU SQ_WAVES); then python3 <repo>/bench.py --traffic-profile <fetch.csv> "
+               "<write.csv> <valu.csv>")
+        rec = write_traffic_profile(*args.traffic_profile, 1 << 30, out, WORKLOADS[args.workload][4], cmd)
+        print(json.dumps(rec, indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU x-slab sharding is design-only)", file=sys.stderr)
