@@ -114,13 +114,15 @@ def job_inputs(superheat, gammas, nx=NX, nyf=NYF, nys=NYS, trigger="spots", P=No
 
 
 def run_curve(superheats, steps=42000, t_a=25000, every=10, precision=pb.PB_FP32_DEV, gammas=None, sigma=None,
-              nx=NX, nyf=NYF, nys=NYS, trigger="spots", log=None):
+              nx=NX, nyf=NYF, nys=NYS, trigger="spots", log=None, chunk=3000):
     """One job per superheat (units of Tc), all stepped in one batched launch
     from the same start; returns a dict with the per-job results and the
     scales used.  trigger "spots": the three nucleate spots on a 55 deg wall
     and a constant T_b (Fig. 11); "fluctuation": a uniform 55 deg wall and
     T_b + 0.02 Tc sin(2 pi (x - l/4) / l), l = nx / 2, for 3000 <= t < 15000
-    (Section 3.2), then constant T_b."""
+    (Section 3.2), then constant T_b.  A job whose run goes non-finite
+    records the end of the first chunk of `chunk` steps after which that was
+    seen (fail_by_t)."""
     if trigger not in ("spots", "fluctuation"):
         raise ValueError("trigger is 'spots' or 'fluctuation'")
     P = paper_params()
@@ -143,20 +145,27 @@ def run_curve(superheats, steps=42000, t_a=25000, every=10, precision=pb.PB_FP32
             doms.append(dom)
         batch = pb.Batch(doms, steps_per_graph=500)
         t0 = time.time()
+        fail_by = [None] * len(doms)   # end of the first chunk after which a job's non-finite flag was seen
         try:
             done = 0
             while done < steps:
-                k = min(6000, steps - done)
+                k = min(chunk, steps - done)
                 batch.step(k)
                 done += k
+                for j, dom in enumerate(doms):
+                    if fail_by[j] is None:
+                        try:
+                            dom.sync()
+                        except pb.NonFiniteError:
+                            fail_by[j] = done
                 if log:
-                    log(f"boiling curve: {done}/{steps} steps queued, {time.time() - t0:.1f} s")
+                    log(f"boiling curve: {done}/{steps} steps, {time.time() - t0:.1f} s")
         finally:
             batch.close()
         s = flux_scale(sigma, P, d, h_fg)
         jobs = []
-        for sh, dom in zip(superheats, doms):
-            rec = dict(superheat_Tc=float(sh), Ja=P["Cv"] * sh * d.Tc / h_fg)
+        for sh, dom, fb in zip(superheats, doms, fail_by):
+            rec = dict(superheat_Tc=float(sh), Ja=P["Cv"] * sh * d.Tc / h_fg, fail_by_t=fb)
             try:
                 dom.sync()
                 hf = dom.heat_flux()
@@ -208,6 +217,49 @@ def film_boiling_nu(run, P=None, d=None):
     return out
 
 
+RECORD_SUPERHEATS = (0.03, 0.06, 0.09, 0.12, 0.15, 0.18, 0.21, 0.24, 0.27, 0.30, 0.33, 0.36, 0.40, 0.41, 0.45)
+FILM_T_B_OVER_TC = 1.27     # Section 3.2: film boiling at T_b = 1.27 Tc
+
+
+def record(superheats=RECORD_SUPERHEATS, log=None):
+    """The boiling curve on the paper's set-up, as a record: the nucleate-spot
+    curve in FP32-deviation and FP64 storage and the fluctuation-trigger curve
+    in FP32-deviation storage, with the same calibrated wall adhesion and the
+    surface tension of Laplace's law; the CHF point of each curve against
+    Zuber (Eq. 40, K = 0.12) and Kandlikar (Eq. 41 at 55 deg), and the
+    film-boiling Nusselt number at T_b = 1.27 Tc against Berenson (Eq. 34).
+    The paper's own figures are carried as context."""
+    P = paper_params()
+    d = paper_derived(P)
+    gammas = calibrated_gammas(P, d)
+    sigma = wetting.surface_tension(params=P, d=d)[0]
+    out = dict(set_up=dict(nx=NX, nyf=NYF, nys=NYS, a=P["a"], varpi=P["varpi"], g=P["g"], s_e=P["s_e"],
+                           s_q=P["s_q"], heater_angle=HEATER_ANGLE, spots=[list(sp) for sp in SPOTS],
+                           spot_width=SPOT_WIDTH, steps=42000, window=[25000, 42001, 10]),
+               gammas_over_psiL={str(k): v / d.psi_L for k, v in gammas.items()}, sigma=sigma,
+               paper=dict(chf_deviation_zuber=0.006, chf_deviation_kandlikar=0.099, Nu_film=54.01,
+                          Nu_berenson=51.28, T_w_film_over_Tc=1.2660))
+    film_sh = FILM_T_B_OVER_TC - 0.86
+    for name, trig, prec in (("spots_fp32", "spots", pb.PB_FP32_DEV), ("fluctuation_fp32", "fluctuation", pb.PB_FP32_DEV),
+                             ("spots_fp64", "spots", pb.PB_FP64)):
+        r = run_curve(list(superheats), precision=prec, gammas=gammas, sigma=sigma, trigger=trig, log=log)
+        r["film_boiling_nu"] = film_boiling_nu(r, P, d)
+        fin = [j for j in r["jobs"] if not j["error"]]
+        chf = max(fin, key=lambda j: j["Q"]) if fin else None
+        summ = dict(finite=len(fin), jobs=len(r["jobs"]))
+        if chf is not None:
+            summ.update(chf_Q=chf["Q"], chf_Ja=chf["Ja"], zuber_012=r["chf"]["zuber_012"],
+                        kandlikar=r["chf"]["kandlikar"], chf_over_zuber=chf["Q"] / r["chf"]["zuber_012"],
+                        chf_over_kandlikar=chf["Q"] / r["chf"]["kandlikar"])
+        for j, nu in zip(r["jobs"], r["film_boiling_nu"]):
+            if abs(j["superheat_Tc"] - film_sh) < 1e-9 and not j["error"]:
+                summ.update(film_T_w_over_Tc=0.86 + j["Tw_minus_Tsat_Tc"], film_Nu=nu["Nu"],
+                            film_Nu_berenson=nu["Nu_berenson"])
+        r["summary"] = summ
+        out[name] = r
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--superheats", default="0.03,0.06,0.09,0.12,0.15,0.18,0.21,0.24,0.27,0.30,0.33,0.36,0.40,0.45",
@@ -216,10 +268,19 @@ def main(argv=None):
     ap.add_argument("--t-a", type=int, default=25000)
     ap.add_argument("--fp64", action="store_true")
     ap.add_argument("--trigger", choices=("spots", "fluctuation"), default="spots")
+    ap.add_argument("--record", metavar="PATH", help="run the three curves of record() and write them to PATH")
     args = ap.parse_args(argv)
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    if args.record:
+        res = record(log=log)
+        with open(args.record, "w") as fh:
+            json.dump(res, fh, indent=1, default=float)
+        for name in ("spots_fp32", "fluctuation_fp32", "spots_fp64"):
+            print(name, json.dumps(res[name]["summary"]), file=sys.stderr)
+        return
     sh = [float(v) for v in args.superheats.split(",")]
     res = run_curve(sh, steps=args.steps, t_a=args.t_a, precision=pb.PB_FP64 if args.fp64 else pb.PB_FP32_DEV,
-                    trigger=args.trigger, log=lambda m: print(m, file=sys.stderr, flush=True))
+                    trigger=args.trigger, log=log)
     res["film_boiling_nu"] = film_boiling_nu(res)
     for j in res["jobs"]:
         print(f"Ja {j['Ja']:.4f}  Q'' {j['Q']:.4f}  Q''(top) {j['Q_top']:.4f}  "
