@@ -80,3 +80,22 @@ def test_long_run_mean_heat_flux_within_3pct(superheat):
     print(f"superheat {superheat}: q_gpu {qg:.6e} q_oracle {qo:.6e} rel {abs(qg - qo) / abs(qo):.2e}", flush=True)
     assert g["flux"]["n_samples"] == o["flux"]["n_samples"] == 151   # t = 1500, 1510, ..., 3000
     assert abs(qg - qo) <= 0.03 * abs(qo)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("shape", [(1 << 20, 3, 3), (2, 1 << 20, 3)])
+def test_largest_domain_sides(shape, precision):
+    """The longest domain sides the library accepts: 2^20 columns (three
+    fluid rows) and 2^20 fluid rows (two columns), three heater rows, the
+    default tiles and strips; 3 steps against the oracle on every field, heat
+    flux sampled every step.  (A side of 2^20 + 1 is refused on the host.)"""
+    nx, nyf, nys = shape
+    print(f"largest sides: {nx} x {nyf} + {nys}, precision {precision}", flush=True)
+    P, d, bc, rho, T = pool_case(nx, nyf, nys, superheat=0.12, n_spots=min(64, nx // 4), seed=5,
+                                 y0=max(1, int(0.4 * nyf)))
+    g, o = run_pair(P, bc, rho, T, steps=3, precision=precision, window=(1, 4, 1))
+    errs = compare(g, o)
+    print(f"largest sides {shape} prec {precision}", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert all(v <= TOL[precision] for v in errs.values()), errs
+    assert g["flux"]["n_samples"] == o["flux"]["n_samples"] == 3
+    assert g["flux"]["q_bottom_mean"] == pytest.approx(o["flux"]["q_bottom_mean"], rel=10 * TOL[precision])
