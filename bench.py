@@ -539,7 +539,7 @@ def main():
         print(f"bench: oracle on {args.cpu_steps} steps", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(nx, nyf, nys, args.cpu_steps)
         if "small_configs" in out:
-            out["cpu_baseline"]["pool_100x100+10"] = cpu_baseline(100, 100, 10, 200)
+            out["cpu_baseline"]["pool_100x100+10"] = cpu_baseline(100, 100, 10, 2000)
         if "serving" in out:
             # the same job mixes on the oracle, one single-thread process per
             # host core (at most 16: the host's share for one GPU)

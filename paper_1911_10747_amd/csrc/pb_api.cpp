@@ -290,14 +290,17 @@ struct pb_batch {
     int nt_flow = 0, nt_th = 0, grid_flow = 0, grid_th = 0;
     int spg = 0, persistent = 0;
     // device tables of the launches, one buffer: descriptor pointers, flow
-    // tiles, energy strips; written from the pinned staging copy htab by an
-    // upload on the batch stream, so they change in stream order
-    char *dtab = nullptr, *htab = nullptr;
-    size_t tab_cap = 0, htab_cap = 0;
+    // tiles, energy strips; written from a pinned staging copy by an upload on
+    // the batch stream, so they change in stream order.  Two staging copies
+    // are used in turn: one is rewritten only after its previous upload (two
+    // membership changes ago) has been read.
+    char *dtab = nullptr, *htab[2] = {nullptr, nullptr};
+    size_t tab_cap = 0, htab_cap[2] = {0, 0};
+    int hslot = 0;
     PbDesc **dptrs = nullptr;
     PbTile *dtiles_flow = nullptr, *dtiles_th = nullptr;
-    hipEvent_t ev_upload = nullptr;   // after the last upload: htab may be rewritten once it has passed
-    bool upload_pending = false;
+    hipEvent_t ev_upload[2] = {nullptr, nullptr};   // after the last upload from each staging copy
+    bool upload_pending[2] = {false, false};
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     std::vector<char> graph_flux;   // steps of the captured graph that launch the flux sample
@@ -918,19 +921,21 @@ int batch_rebuild(pb_batch *b) {
     const size_t o_tf = align_up((size_t)std::max(n, 1) * sizeof(PbDesc *), kAlign);
     const size_t o_tt = o_tf + align_up(std::max<size_t>(1, tf.size()) * sizeof(PbTile), kAlign);
     const size_t total = o_tt + align_up(std::max<size_t>(1, tt.size()) * sizeof(PbTile), kAlign);
-    // the staging copy is rewritten only after the previous upload has read it
-    if (b->upload_pending) {
-        PB_HIP(hipEventSynchronize(b->ev_upload));
-        b->upload_pending = false;
+    // the staging copy is rewritten only after its previous upload has read it
+    const int hs = b->hslot ^ 1;
+    if (b->upload_pending[hs]) {
+        PB_HIP(hipEventSynchronize(b->ev_upload[hs]));
+        b->upload_pending[hs] = false;
     }
-    if (total > b->htab_cap) {
-        if (b->htab) PB_HIP(hipHostFree(b->htab));
-        b->htab = nullptr;
-        b->htab_cap = 0;
-        if (hipHostMalloc((void **)&b->htab, 2 * total, hipHostMallocDefault) != hipSuccess)
+    if (total > b->htab_cap[hs]) {
+        if (b->htab[hs]) PB_HIP(hipHostFree(b->htab[hs]));
+        b->htab[hs] = nullptr;
+        b->htab_cap[hs] = 0;
+        if (hipHostMalloc((void **)&b->htab[hs], 2 * total, hipHostMallocDefault) != hipSuccess)
             return fail(PB_ENOMEM, "pinned staging of %zu bytes failed", 2 * total);
-        b->htab_cap = 2 * total;
+        b->htab_cap[hs] = 2 * total;
     }
+    char *const stage = b->htab[hs];
     char *old_tab = nullptr;
     if (total > b->tab_cap) {
         char *t = nullptr;
@@ -940,16 +945,17 @@ int batch_rebuild(pb_batch *b) {
         b->dtab = t;
         b->tab_cap = 2 * total;
     }
-    memcpy(b->htab, ptrs.data(), (size_t)n * sizeof(PbDesc *));
-    memcpy(b->htab + o_tf, tf.data(), tf.size() * sizeof(PbTile));
-    memcpy(b->htab + o_tt, tt.data(), tt.size() * sizeof(PbTile));
+    memcpy(stage, ptrs.data(), (size_t)n * sizeof(PbDesc *));
+    memcpy(stage + o_tf, tf.data(), tf.size() * sizeof(PbTile));
+    memcpy(stage + o_tt, tt.data(), tt.size() * sizeof(PbTile));
     // what was captured or queued before reads the previous tables (and
     // buffer): retire them behind that work
     int rc = batch_retire(b, old_tab);
     if (rc) return rc;
-    PB_HIP(hipMemcpyAsync(b->dtab, b->htab, total, hipMemcpyHostToDevice, b->stream));
-    PB_HIP(hipEventRecord(b->ev_upload, b->stream));
-    b->upload_pending = true;
+    PB_HIP(hipMemcpyAsync(b->dtab, stage, total, hipMemcpyHostToDevice, b->stream));
+    PB_HIP(hipEventRecord(b->ev_upload[hs], b->stream));
+    b->upload_pending[hs] = true;
+    b->hslot = hs;
     b->dptrs = (PbDesc **)b->dtab;
     b->dtiles_flow = (PbTile *)(b->dtab + o_tf);
     b->dtiles_th = (PbTile *)(b->dtab + o_tt);
@@ -1010,7 +1016,8 @@ int pb_batch_create(pb_domain *const *doms, int32_t n, int32_t steps_per_graph, 
     }
     if (!rc && (hipEventCreateWithFlags(&b->ev_batch, hipEventDisableTiming) != hipSuccess ||
                 hipEventCreateWithFlags(&b->ev_dom, hipEventDisableTiming) != hipSuccess ||
-                hipEventCreateWithFlags(&b->ev_upload, hipEventDisableTiming) != hipSuccess))
+                hipEventCreateWithFlags(&b->ev_upload[0], hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&b->ev_upload[1], hipEventDisableTiming) != hipSuccess))
         rc = fail(PB_EDEVICE, "event creation failed");
     if (!rc) rc = batch_rebuild(b);
     if (rc) {
@@ -1151,10 +1158,12 @@ void pb_batch_destroy(pb_batch *b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->ev_batch) (void)hipEventDestroy(b->ev_batch);
     if (b->ev_dom) (void)hipEventDestroy(b->ev_dom);
-    if (b->ev_upload) (void)hipEventDestroy(b->ev_upload);
+    for (int h = 0; h < 2; ++h)
+        if (b->ev_upload[h]) (void)hipEventDestroy(b->ev_upload[h]);
     if (b->owns_stream) (void)hipStreamDestroy(b->stream);
     if (b->dtab) (void)hipFree(b->dtab);
-    if (b->htab) (void)hipHostFree(b->htab);
+    for (int h = 0; h < 2; ++h)
+        if (b->htab[h]) (void)hipHostFree(b->htab[h]);
     delete b;
 }
 
