@@ -156,3 +156,16 @@ def test_energy_work_list_ends_with_short_strips():
     assert set(w[:, 3]) == {8}
     with pytest.raises(pb.PbError):
         pb.thermal_work_list([six[0], cfg(nx=100, ny_fluid=100, ny_solid=10, precision=0)])
+
+
+def test_null_handles_refused_without_gpu():
+    """The batch-membership calls and the allocation-free read check their
+    handles on the host before any device work."""
+    from paper_1911_10747_amd import poolboil as pb
+    assert pb.lib.pb_batch_add(None, None) == pb.PB_EINVAL
+    assert pb.lib.pb_batch_remove(None, None) == pb.PB_EINVAL
+    assert pb.lib.pb_batch_size(None) == -1
+    assert pb.lib.pb_batch_step(None, 1) == pb.PB_EINVAL
+    assert pb.lib.pb_read_fields_noalloc(None, None, None, None, None, None) == pb.PB_EINVAL
+    assert pb.lib.pb_read_fields(None, None, None, None, None, None) == pb.PB_EINVAL
+    assert "NULL" in pb.lib.pb_last_error().decode()
