@@ -63,9 +63,9 @@ enum {
  * up to the rounding of the deviation; T stays FP64.  The flow step (moments,
  * psi and the EOS, forces, collision) computes in FP64 in both modes;
  * with PB_FP32_DEV the energy equation computes its operator and stages in
- * FP32 as increments over the FP64 T (FP64 for the EOS derivative, the
- * differences T(x + e_i) - T(x) and the update), within the FP32 tolerance
- * of the oracle comparisons. */
+ * FP32 as increments over the FP64 T (FP64 for the differences
+ * T(x + e_i) - T(x) and the update), within the FP32 tolerance of the
+ * oracle comparisons. */
 enum { PB_FP64 = 0, PB_FP32_DEV = 1 };
 
 /* Configuration flags (pb_config.flags). */

@@ -868,6 +868,7 @@ __device__ __forceinline__ void thermal_strip_sp(cdesc &d, const PbTile &te, int
     const float cvchi = (float)d.Cvchi, lam_s = (float)d.lambda_S, cv = (float)d.Cv;
     const float c1_solid = (float)(1.0 / (d.rho_S * d.C_S));
     const float lat_a = (float)(d.kappa / d.Tc), lat_b = (float)((1.0 + d.kappa) * d.inv_sqrtTc);
+    const float eos_b = (float)d.b, eos_R = (float)d.R, eos_ak = (float)(d.a * d.kappa);
     const float W1 = 6.0f / 9.0f, W2 = 6.0f / 36.0f, A1 = 3.0f / 9.0f, A2 = 3.0f / 36.0f;
 
     // carried state; "_1" = row n-1, "_2" = row n-2 and so on
@@ -878,6 +879,7 @@ __device__ __forceinline__ void thermal_strip_sp(cdesc &d, const PbTile &te, int
     float p_1 = 0.0f, m_1 = 0.0f, p_2 = 0.0f, m_2 = 0.0f;
     float lN_2 = 0.0f, lNEL_2 = 0.0f, lNWR_2 = 0.0f;
     double T0_1 = 0.0, T0_2 = 0.0, T0_3 = 0.0, T0_4 = 0.0;
+    float Tf_1 = 0.0f, Tf_2 = 0.0f, Tf_3 = 0.0f, Tf_4 = 0.0f;   // the same rows rounded to FP32
     // FP64 differences rounded to FP32: T(x+1) - T(x) and T(x-1) - T(x) of a
     // row, and T(row n-1) - T(row n-2)
     float dR_1 = 0.0f, dL_1 = 0.0f, dR_2 = 0.0f, dL_2 = 0.0f, dV_1 = 0.0f;
@@ -909,15 +911,21 @@ __device__ __forceinline__ void thermal_strip_sp(cdesc &d, const PbTile &te, int
         const float dV = (float)(cur.T0 - T0_1);
         const float p = cur.vx + cur.vy, m = cur.vx - cur.vy;
 
-        // operator of row a = n-1: the four link sums and rho C_V share one
-        // reciprocal (batch inversion); A(rho), B(rho) in FP64
+        // operator of row a = n-1: the four link sums, rho C_V and the
+        // Peng-Robinson denominator (1 - b rho)(1 + 2 b rho - b^2 rho^2) share
+        // one reciprocal (batch inversion)
         const float sE = lam_1 + lamR_1, sN = lam_1 + cur.lam, sNE = lam_1 + lamR, sNW = lam_1 + lamL;
         const bool fluid_1 = FL || kind_1 == KIND_FLUID;
         const float dE = hlink_div<FL>(lam_1, lamR_1, sE), dN = hlink_div<FL>(lam_1, cur.lam, sN);
         const float dNE = hlink_div<FL>(lam_1, lamR, sNE), dNW = hlink_div<FL>(lam_1, lamL, sNW);
         const float dC = fluid_1 ? rho_1 * cv : 1.0f;
-        const float p1 = dE * dN, p2 = p1 * dNE, p3 = p2 * dNW, p4 = p3 * dC;
-        float rr = frcp_s(p4);
+        const float br = eos_b * rho_1;
+        const float q1 = 1.0f - br, q2 = 1.0f + br * (2.0f - br);
+        const float dQ = fluid_1 ? q1 * q2 : 1.0f;
+        const float p1 = dE * dN, p2 = p1 * dNE, p3 = p2 * dNW, p4 = p3 * dC, p5 = p4 * dQ;
+        float rr = frcp_s(p5);
+        const float iQ = rr * p4;
+        rr = rr * dQ;
         const float iC = rr * p3;
         rr = rr * dC;
         const float iNW = rr * p2;
@@ -942,11 +950,8 @@ __device__ __forceinline__ void thermal_strip_sp(cdesc &d, const PbTile &te, int
             cf.k1 = c1; cf.k2 = c2; cf.k3 = c3; cf.k4 = c4;
             cf.k5 = c5; cf.k6 = c6; cf.k7 = c7; cf.k8 = c8;
             if (fluid_1) {
-                const double r1 = rho_1, br = d.b * r1;
-                const double q1 = 1.0 - br, q2 = 1.0 + 2.0 * br - br * br;
-                const double iq = frcp(q1 * q2);
-                const float A = (float)(r1 * d.R * q2 * iq);                  // rho R / (1 - b rho)
-                const float B = (float)(d.a * d.kappa * r1 * r1 * q1 * iq);   // a kappa rho^2 / (1 + 2 b rho - b^2 rho^2)
+                const float A = eos_R * rho_1 * q2 * iQ;              // rho R / (1 - b rho)
+                const float B = eos_ak * rho_1 * rho_1 * q1 * iQ;     // a kappa rho^2 / (1 + 2 b rho - b^2 rho^2)
                 const float divv = 3.0f * ((UR - VL) + (1.0f / 9.0f) * (cur.vy - vy_2));
                 const float AL = -C1 * divv * A, BE = -C1 * divv * B;
                 lin = AL - BE * lat_a;
@@ -962,7 +967,6 @@ __device__ __forceinline__ void thermal_strip_sp(cdesc &d, const PbTile &te, int
 
         // stage 1 on row n-1 from the differences to T(x) (input T rows n-2,
         // n-1, n); a diagonal difference is a row difference plus a column one
-        const float Tf_1 = (float)T0_1;
         const float dS = -dV_1;
         const float LT = (cf.k1 * dR_1 + cf.k3 * dL_1) + (cf.k2 * dV + cf.k5 * (dV + dR) + cf.k6 * (dV + dL)) +
                          (cf.k4 * dS + cf.k7 * (dS + dL_2) + cf.k8 * (dS + dR_2)) + lin * Tf_1;
@@ -971,17 +975,17 @@ __device__ __forceinline__ void thermal_strip_sp(cdesc &d, const PbTile &te, int
         const float acc1 = h1;
         const float h1L = from_left(h1), h1R = from_right(h1);
         // stage 2 on row n-2 (input h1 rows n-3, n-2, n-1)
-        const float h2 = stage_s<FL>(cf_2, kd_2, LT_2, 0.5f, (float)T0_2, h1_2, h1R_2, h1L_2, h1, h1R, h1L, h1_3,
+        const float h2 = stage_s<FL>(cf_2, kd_2, LT_2, 0.5f, Tf_2, h1_2, h1R_2, h1L_2, h1, h1R, h1L, h1_3,
                                      h1R_3, h1L_3);
         const float acc2 = acc_2 + 2.0f * h2;
         const float h2L = from_left(h2), h2R = from_right(h2);
         // stage 3 on row n-3 (input h2 rows n-4, n-3, n-2)
-        const float h3 = stage_s<FL>(cf_3, kd_3, LT_3, 0.5f, (float)T0_3, h2_3, h2R_3, h2L_3, h2, h2R, h2L, h2_4,
+        const float h3 = stage_s<FL>(cf_3, kd_3, LT_3, 0.5f, Tf_3, h2_3, h2R_3, h2L_3, h2, h2R, h2L, h2_4,
                                      h2R_4, h2L_4);
         const float acc3 = acc_3 + 2.0f * h3;
         const float h3L = from_left(h3), h3R = from_right(h3);
         // stage 4 and the update on row e = n-4 (input h3 rows n-5, n-4, n-3)
-        const float h4 = stage_s<FL>(cf_4, kd_4, LT_4, 1.0f, (float)T0_4, h3_4, h3R_4, h3L_4, h3, h3R, h3L, h3_5,
+        const float h4 = stage_s<FL>(cf_4, kd_4, LT_4, 1.0f, Tf_4, h3_4, h3R_4, h3L_4, h3, h3R, h3L, h3_5,
                                      h3R_5, h3L_5);
         const int e = n - 4;
         if constexpr (FL) {
@@ -1018,6 +1022,7 @@ __device__ __forceinline__ void thermal_strip_sp(cdesc &d, const PbTile &te, int
         acc_4 = acc3; acc_3 = acc2; acc_2 = acc1;
         kd_4 = kd_3; kd_3 = kd_2; kd_2 = kind_1;
         T0_4 = T0_3; T0_3 = T0_2; T0_2 = T0_1; T0_1 = cur.T0;
+        Tf_4 = Tf_3; Tf_3 = Tf_2; Tf_2 = Tf_1; Tf_1 = (float)cur.T0;
         dR_2 = dR_1; dL_2 = dL_1; dR_1 = dR; dL_1 = dL; dV_1 = dV;
         lN_2 = lN; lNEL_2 = from_left(lNE); lNWR_2 = from_right(lNW);
         vy_2 = vy_1; p_2 = p_1; m_2 = m_1;
