@@ -146,30 +146,21 @@ def kernel_record(rec, prefix):
     return None
 
 
-# VALU issue: 256 CUs x 4 SIMDs at 2.4 GHz; a wavefront-64 FP64 instruction
-# every 4 cycles per SIMD -> 614.4 G wavefront instructions/s (78.6 TFLOP/s of
-# FP64 FMA), a non-packed FP32 one every 2 cycles -> 1228.8 G/s.
-VALU_PEAK_F64_GINST = 256 * 4 / 4 * 2.4
-VALU_PEAK_F32_GINST = 256 * 4 / 2 * 2.4
-# With FP32-deviation storage the energy-equation sweep computes in FP32; in
-# its compiled fluid-strip loop 19% of the VALU instructions are FP64 or
-# FP64<->FP32 conversions (4-cycle issue), the rest FP32.
-THERMAL_F64_SHARE_FP32DEV = 0.19
-
-
-def thermal_valu_peak(prec):
-    if prec == 0:
-        return VALU_PEAK_F64_GINST
-    f = THERMAL_F64_SHARE_FP32DEV
-    return 1.0 / (f / VALU_PEAK_F64_GINST + (1.0 - f) / VALU_PEAK_F32_GINST)
+# VALU issue: 256 CUs x 4 SIMDs at 2.4 GHz, one wavefront-64 instruction every
+# 4 cycles per SIMD (16 lanes) -> 614.4 G wavefront instructions/s, for FP64
+# (78.6 TFLOP/s of FP64 FMA) and for non-packed FP32 alike (the 157.3 TFLOP/s
+# FP32 figure counts packed FP32, two operations per lane, which this build
+# does not use).  Measured on the box with independent FMA chains at 3-8 waves
+# per SIMD: 0.22-0.24 wave instructions per SIMD-cycle for both.
+VALU_PEAK_GINST = 256 * 4 / 4 * 2.4
 
 
 def per_kernel(nx, nyf, nys, prec, prof, rec):
     """Each launch against the roof that bounds it: k_flow against HBM
     (algorithmic bytes: populations in + out and the T read per fluid node;
     measured bytes from the counters), k_thermal_sweep against VALU issue
-    (measured wavefront VALU instructions per launch over the issue rate of its
-    instruction mix) with its HBM figures beside."""
+    (measured wavefront VALU instructions per launch over the chip's issue
+    rate) with its HBM figures beside."""
     flow_alg = ((144 if prec == 0 else 72) + 8) * nx * nyf
     th_alg = 16 * nx * (nyf + nys)
     out = {}
@@ -184,9 +175,8 @@ def per_kernel(nx, nyf, nys, prec, prof, rec):
             k["traffic_gbs"] = round(kr["total_bytes"] / (ms * 1e-3) / 1e9, 1)
             if kr.get("valu_insts"):
                 k["valu_ginst_s"] = round(kr["valu_insts"] / (ms * 1e-3) / 1e9, 1)
-                peak = VALU_PEAK_F64_GINST if name == "k_flow" else thermal_valu_peak(prec)
-                k["valu_peak_ginst_s"] = round(peak, 1)
-                k["frac_valu"] = round(kr["valu_insts"] / (ms * 1e-3) / 1e9 / peak, 4)
+                k["valu_peak_ginst_s"] = round(VALU_PEAK_GINST, 1)
+                k["frac_valu"] = round(kr["valu_insts"] / (ms * 1e-3) / 1e9 / VALU_PEAK_GINST, 4)
         out[name] = k
     return out
 

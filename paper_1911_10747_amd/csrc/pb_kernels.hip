@@ -788,17 +788,27 @@ struct RowInS {
     float rho, lam, vx, vy;   // rho as stored: converted where used, so a prefetch does not wait on it
 };
 
+// Element x of row r of a plane: a row address computed in scalar registers
+// plus the lane's byte offset (xb = 4 x or 8 x, a 32-bit value fixed for the
+// strip), so a row load costs no vector address arithmetic.
+template <typename V>
+__device__ __forceinline__ V row_elem(const V PB_GAS *base, uint32_t row, uint32_t pitch, uint32_t xb) {
+    const char PB_GAS *rb = (const char PB_GAS *)(base + (size_t)(row * pitch));
+    return *(const V PB_GAS *)(rb + xb);
+}
+
 template <bool FL>
 __device__ __forceinline__ RowInS load_row_s(cdesc &d, const double PB_GAS *Tin, const float PB_GAS *rho,
-                                             const float PB_GAS *vxg, const float PB_GAS *vyg, int n, int xg,
+                                             const float PB_GAS *vxg, const float PB_GAS *vyg, int n, uint32_t xb4,
                                              bool pery, float lam_s) {
     RowInS r{KIND_NONE, 0.0, 0.0f, 0.0f, 0.0f, 0.0f};
+    const uint32_t pitch = (uint32_t)d.pitch, xb8 = xb4 * 2u;
     if constexpr (FL) {
-        const uint32_t fi = (uint32_t)(n - d.nys) * (uint32_t)d.pitch + (uint32_t)xg;
-        r.T0 = Tin[(uint32_t)n * (uint32_t)d.pitch + (uint32_t)xg];
-        r.rho = rho[fi];
-        r.vx = vxg[fi];
-        r.vy = vyg[fi];
+        const uint32_t fr = (uint32_t)(n - d.nys);
+        r.T0 = row_elem(Tin, (uint32_t)n, pitch, xb8);
+        r.rho = row_elem(rho, fr, pitch, xb4);
+        r.vx = row_elem(vxg, fr, pitch, xb4);
+        r.vy = row_elem(vyg, fr, pitch, xb4);
         r.kind = KIND_FLUID;
         return r;
     }
@@ -808,15 +818,15 @@ __device__ __forceinline__ RowInS load_row_s(cdesc &d, const double PB_GAS *Tin,
         if (rr < 0) rr += d.nr;
     }
     if (rr >= 0 && rr < d.nr) {
-        r.T0 = Tin[(uint32_t)rr * (uint32_t)d.pitch + (uint32_t)xg];
+        r.T0 = row_elem(Tin, (uint32_t)rr, pitch, xb8);
         if (rr < d.nys) {
             r.lam = lam_s;
             r.kind = (rr == 0 && !pery) ? KIND_FIXED : KIND_SOLID;
         } else {
-            const uint32_t fi = (uint32_t)(rr - d.nys) * (uint32_t)d.pitch + (uint32_t)xg;
-            r.rho = rho[fi];
-            r.vx = vxg[fi];
-            r.vy = vyg[fi];
+            const uint32_t fr = (uint32_t)(rr - d.nys);
+            r.rho = row_elem(rho, fr, pitch, xb4);
+            r.vx = row_elem(vxg, fr, pitch, xb4);
+            r.vy = row_elem(vyg, fr, pitch, xb4);
             r.kind = KIND_FLUID;
         }
     } else if (!pery && rr == d.nr) {
@@ -865,6 +875,7 @@ __device__ __forceinline__ void thermal_strip_sp(cdesc &d, const PbTile &te, int
     if (xg < 0) xg += d.nx;
     const bool out_lane = lane >= 4 && lane < 60 && (te.x0 + lane - 4) < d.nx;
     double PB_GAS *Tst = out_lane ? Tout : gcast_w<double>(d.sink);
+    const uint32_t xb4 = (uint32_t)xg * 4u;
     const float cvchi = (float)d.Cvchi, lam_s = (float)d.lambda_S, cv = (float)d.Cv;
     const float c1_solid = (float)(1.0 / (d.rho_S * d.C_S));
     const float lat_a = (float)(d.kappa / d.Tc), lat_b = (float)((1.0 + d.kappa) * d.inv_sqrtTc);
@@ -893,14 +904,14 @@ __device__ __forceinline__ void thermal_strip_sp(cdesc &d, const PbTile &te, int
     bool bad = false;
 
     const int nbeg = te.y0 - 4, nend = te.y0 + H + 3;
-    RowInS nx1 = load_row_s<FL>(d, Tin, rhog, vxg, vyg, nbeg, xg, pery, lam_s);
-    RowInS nx2 = load_row_s<FL>(d, Tin, rhog, vxg, vyg, nbeg + 1, xg, pery, lam_s);
+    RowInS nx1 = load_row_s<FL>(d, Tin, rhog, vxg, vyg, nbeg, xb4, pery, lam_s);
+    RowInS nx2 = load_row_s<FL>(d, Tin, rhog, vxg, vyg, nbeg + 1, xb4, pery, lam_s);
 #pragma unroll UNR
     for (int j = 0; j < H + 8; ++j) {
         const int n = nbeg + j;
         RowInS cur = nx1;
         nx1 = nx2;
-        if (n + 2 <= nend) nx2 = load_row_s<FL>(d, Tin, rhog, vxg, vyg, n + 2, xg, pery, lam_s);
+        if (n + 2 <= nend) nx2 = load_row_s<FL>(d, Tin, rhog, vxg, vyg, n + 2, xb4, pery, lam_s);
         // keep the loads of row n+2 here: the scheduler would otherwise sink
         // them next to their use to save registers and lose the prefetch
         __builtin_amdgcn_sched_barrier(0);
