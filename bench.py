@@ -466,6 +466,7 @@ def main():
     dom.flux_window(0, 1 << 62, 10)
     print(f"bench: {args.workload} {nx}x{nyf}+{nys} prec={prec}: warmup {args.warmup}", file=sys.stderr, flush=True)
     dom.step(args.warmup)
+    dom.profile_reserve(args.steps)     # the timed steps' HIP events, created before the clock starts
     dom.sync()
     torch.cuda.synchronize()
     print(f"bench: timing {args.steps} steps", file=sys.stderr, flush=True)

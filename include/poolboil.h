@@ -207,8 +207,14 @@ int pb_heat_flux(pb_domain *dom, pb_flux *out);   /* synchronous */
  * recorded on the domain's stream around every flow and thermal launch; wait
  * for them and return the mean launch durations in milliseconds:
  * avg_ms[0] = flow kernel, avg_ms[1] = thermal kernel, avg_ms[2] = elapsed
- * time of the whole sequence divided by n.  The steps are real steps. */
+ * time of the whole sequence divided by n.  The steps are real steps.  The
+ * events (2n + 1) stay with the domain and are reused by later calls; the
+ * ones missing are created first, on the current device.
+ * pb_profile_reserve creates them for up to n steps ahead of time, so that a
+ * timed call creates none.  n in [1, 2^20]; PB_EDEVICE if an event cannot be
+ * created. */
 int pb_profile_steps(pb_domain *dom, int64_t n, double *avg_ms);
+int pb_profile_reserve(pb_domain *dom, int64_t n);
 
 int64_t pb_time(const pb_domain *dom);            /* current t              */
 double pb_rho_bar(const pb_domain *dom);          /* rho_bar of Eq. 15      */

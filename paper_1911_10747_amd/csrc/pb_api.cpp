@@ -280,6 +280,7 @@ struct pb_domain {
     PbTile *dtiles_flow = nullptr, *dtiles_th = nullptr;
     std::vector<double> Tb, Tba, gb, gt;
     double *rd = nullptr;        // read-back staging of pb_read_fields (lazy)
+    std::vector<hipEvent_t> prof_ev;   // events of pb_profile_steps, kept for reuse
 };
 
 struct pb_batch {
@@ -547,6 +548,7 @@ int pb_create_domain(const pb_config *cfg, void *stream, void *dev_mem, size_t d
 void pb_destroy_domain(pb_domain *d) {
     if (!d) return;
     (void)hipStreamSynchronize(d->stream);
+    for (hipEvent_t e : d->prof_ev) (void)hipEventDestroy(e);
     if (d->rd) (void)hipFree(d->rd);
     if (d->owns) (void)hipFree(d->base);
     delete d;
@@ -789,25 +791,32 @@ int pb_heat_flux(pb_domain *d, pb_flux *out) {
     return PB_OK;
 }
 
+int pb_profile_reserve(pb_domain *d, int64_t n) {
+    int rc = check_dom(d);
+    if (rc) return rc;
+    if (n < 1 || n > (1 << 20)) return fail(PB_EINVAL, "n must be in [1, 2^20]");
+    while (d->prof_ev.size() < 2 * (size_t)n + 1) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return fail(PB_EDEVICE, "event creation failed");
+        d->prof_ev.push_back(e);
+    }
+    return PB_OK;
+}
+
 int pb_profile_steps(pb_domain *d, int64_t n, double *avg_ms) {
     int rc = check_dom(d);
     if (rc) return rc;
     if (!d->fields_set) return fail(PB_ESTATE, "pb_set_fields was not called");
     if (!avg_ms) return fail(PB_EINVAL, "avg_ms is NULL");
     if (n < 1 || n > (1 << 20)) return fail(PB_EINVAL, "n must be in [1, 2^20]");
+    if ((rc = pb_profile_reserve(d, n))) return rc;
     const bool frozen = d->cfg.flags & PB_FROZEN_FLOW, iso = d->cfg.flags & PB_ISOTHERMAL;
     const bool sampling = !(d->cfg.flags & PB_PERIODIC_Y) && d->cfg.ny_solid >= 1 && d->hd.fl_tb > d->hd.fl_ta;
     const PbDesc *const *dp = (const PbDesc *const *)d->dptr;
     const int m = (int)n;
     // events e[2k] before the flow launch of step k, e[2k+1] between flow and
     // thermal, e[2k+2] after the thermal launch
-    std::vector<hipEvent_t> ev(2 * (size_t)m + 1, nullptr);
-    auto release = [&]() {
-        for (hipEvent_t e : ev)
-            if (e) (void)hipEventDestroy(e);
-    };
-    for (auto &e : ev)
-        if (hipEventCreate(&e) != hipSuccess) { release(); return fail(PB_EDEVICE, "event creation failed"); }
+    const std::vector<hipEvent_t> &ev = d->prof_ev;
     hipError_t err = hipSuccess;
     for (int k = 0; k < m && err == hipSuccess; ++k) {
         err = hipEventRecord(ev[2 * k], d->stream);
@@ -824,7 +833,7 @@ int pb_profile_steps(pb_domain *d, int64_t n, double *avg_ms) {
     if (err == hipSuccess) err = hipEventRecord(ev[2 * m], d->stream);
     if (err == hipSuccess) err = pb_launch_advance(d->dptr, 1, m, d->stream);
     if (err == hipSuccess) err = hipStreamSynchronize(d->stream);
-    if (err != hipSuccess) { release(); return fail(PB_EDEVICE, "profiled steps failed: %s", hipGetErrorString(err)); }
+    if (err != hipSuccess) return fail(PB_EDEVICE, "profiled steps failed: %s", hipGetErrorString(err));
     d->t += m;
     d->par ^= (m & 1);
     d->hd.t0 = d->t;
@@ -841,7 +850,6 @@ int pb_profile_steps(pb_domain *d, int64_t n, double *avg_ms) {
     avg_ms[0] = sf / m;
     avg_ms[1] = st / m;
     avg_ms[2] = (double)ms / m;
-    release();
     return PB_OK;
 }
 

@@ -19,7 +19,7 @@ PB_PERIODIC_Y, PB_ISOTHERMAL, PB_FROZEN_FLOW, PB_SBAR2_PLUS, PB_VARPI_FM_ONLY = 
 
 EXPORTED = [
     "pb_domain_bytes", "pb_thermal_strip_rows", "pb_thermal_work_list", "pb_create_domain", "pb_destroy_domain", "pb_set_bc", "pb_set_fields", "pb_set_fields_full",
-    "pb_step", "pb_sync", "pb_read_fields", "pb_read_fields_noalloc", "pb_flux_window", "pb_heat_flux", "pb_profile_steps", "pb_time",
+    "pb_step", "pb_sync", "pb_read_fields", "pb_read_fields_noalloc", "pb_flux_window", "pb_heat_flux", "pb_profile_steps", "pb_profile_reserve", "pb_time",
     "pb_rho_bar",
     "pb_batch_create", "pb_batch_step", "pb_batch_destroy", "pb_batch_add", "pb_batch_remove", "pb_batch_size", "pb_eos_critical_temperature", "pb_eos_coexistence",
     "pb_eos_psi", "pb_eos_latent_heat", "pb_last_error", "pb_version",
@@ -95,6 +95,7 @@ def _load():
         "pb_flux_window": ([vp, i64, i64, i32], C.c_int),
         "pb_heat_flux": ([vp, C.POINTER(Flux)], C.c_int),
         "pb_profile_steps": ([vp, i64, dp], C.c_int),
+        "pb_profile_reserve": ([vp, i64], C.c_int),
         "pb_time": ([vp], i64),
         "pb_rho_bar": ([vp], C.c_double),
         "pb_batch_create": ([C.POINTER(vp), i32, i32, i32, vp, C.POINTER(vp)], C.c_int),
@@ -287,6 +288,11 @@ class Domain:
         out = (C.c_double * 3)()
         _check(lib.pb_profile_steps(self._h, int(n), out))
         return dict(flow_ms=out[0], thermal_ms=out[1], step_ms=out[2])
+
+    def profile_reserve(self, n):
+        """Create the events of profile_steps(n) now (they stay with the
+        domain), so that a timed profile_steps creates none."""
+        _check(lib.pb_profile_reserve(self._h, int(n)))
 
     @property
     def t(self):

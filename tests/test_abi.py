@@ -168,4 +168,6 @@ def test_null_handles_refused_without_gpu():
     assert pb.lib.pb_batch_step(None, 1) == pb.PB_EINVAL
     assert pb.lib.pb_read_fields_noalloc(None, None, None, None, None, None) == pb.PB_EINVAL
     assert pb.lib.pb_read_fields(None, None, None, None, None, None) == pb.PB_EINVAL
+    assert pb.lib.pb_profile_reserve(None, 1) == pb.PB_EINVAL
+    assert pb.lib.pb_profile_steps(None, 1, None) == pb.PB_EINVAL
     assert "NULL" in pb.lib.pb_last_error().decode()
