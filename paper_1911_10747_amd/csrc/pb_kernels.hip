@@ -311,7 +311,7 @@ __device__ __forceinline__ bool node_update(cdesc &d, const double f[9], const M
         st.pop(8, encode_pop<FT>(8, cd + a3 + a4 - a5 - a6 - a8, rref));
         st.fields(rho, (FT)vx, (FT)vy);      // rho and v in FP32 with FP32 storage
     }
-    return !(rho == rho) || !(vx - vx == 0.0) || !(vy - vy == 0.0);
+    return !(rho == rho) || !__builtin_isfinite(vx) || !__builtin_isfinite(vy);
 }
 
 // ---------------------------------------------------------------- flow step
@@ -735,7 +735,7 @@ __device__ __forceinline__ void thermal_strip(cdesc &d, const PbTile &te, int k,
                 Tn = T0_4 + (1.0 / 6.0) * (acc_4 + K4);
             }
             Tout[(uint32_t)e * (uint32_t)d.pitch + (uint32_t)xg] = Tn;
-            bad = bad || !(Tn - Tn == 0.0);
+            bad = bad || !__builtin_isfinite(Tn);
         }
 
         // shift the windows by one row
@@ -842,13 +842,20 @@ __device__ __forceinline__ float frcp_s(float x) {
     return __builtin_fmaf(__builtin_fmaf(-x, r, 1.0f), r, r);
 }
 
-// L applied to nine values (centre row S*, row above N*, row below *_)
+// L applied to nine values (centre row S*, row above N*, row below *_): one
+// multiply-add chain, the centre and lower rows (known a row earlier) first,
+// so the row above, computed last, enters through three multiply-adds
 __device__ __forceinline__ float lin9s(const Coef9s &c, float Sc, float SR, float SL, float Nc, float NR, float NL,
                                        float Sc_, float SR_, float SL_) {
-    const float rm = c.k0 * Sc + c.k1 * SR + c.k3 * SL;
-    const float ra = c.k2 * Nc + c.k5 * NR + c.k6 * NL;
-    const float rb = c.k4 * Sc_ + c.k7 * SL_ + c.k8 * SR_;
-    return rm + (ra + rb);
+    float r = c.k0 * Sc;
+    r = __builtin_fmaf(c.k1, SR, r);
+    r = __builtin_fmaf(c.k3, SL, r);
+    r = __builtin_fmaf(c.k4, Sc_, r);
+    r = __builtin_fmaf(c.k7, SL_, r);
+    r = __builtin_fmaf(c.k8, SR_, r);
+    r = __builtin_fmaf(c.k2, Nc, r);
+    r = __builtin_fmaf(c.k5, NR, r);
+    return __builtin_fmaf(c.k6, NL, r);
 }
 
 // stage k >= 2: h_k = L T + c L h_(k-1) + beta sqrt(T + c h_(k-1)); sqrt is
@@ -979,8 +986,15 @@ __device__ __forceinline__ void thermal_strip_sp(cdesc &d, const PbTile &te, int
         // stage 1 on row n-1 from the differences to T(x) (input T rows n-2,
         // n-1, n); a diagonal difference is a row difference plus a column one
         const float dS = -dV_1;
-        const float LT = (cf.k1 * dR_1 + cf.k3 * dL_1) + (cf.k2 * dV + cf.k5 * (dV + dR) + cf.k6 * (dV + dL)) +
-                         (cf.k4 * dS + cf.k7 * (dS + dL_2) + cf.k8 * (dS + dR_2)) + lin * Tf_1;
+        float LT = lin * Tf_1;
+        LT = __builtin_fmaf(cf.k1, dR_1, LT);
+        LT = __builtin_fmaf(cf.k3, dL_1, LT);
+        LT = __builtin_fmaf(cf.k4, dS, LT);
+        LT = __builtin_fmaf(cf.k7, dS + dL_2, LT);
+        LT = __builtin_fmaf(cf.k8, dS + dR_2, LT);
+        LT = __builtin_fmaf(cf.k2, dV, LT);
+        LT = __builtin_fmaf(cf.k5, dV + dR, LT);
+        LT = __builtin_fmaf(cf.k6, dV + dL, LT);
         float h1 = LT;
         if (FL || kind_1 == KIND_FLUID) h1 += cf.beta * __builtin_amdgcn_sqrtf(Tf_1);
         const float acc1 = h1;
@@ -1007,7 +1021,7 @@ __device__ __forceinline__ void thermal_strip_sp(cdesc &d, const PbTile &te, int
                 const double Tn = T0_4 + (double)((1.0f / 6.0f) * (acc_4 + h4));
                 const uint32_t off = out_lane ? (uint32_t)e * (uint32_t)d.pitch + (uint32_t)xg : (uint32_t)lane;
                 Tst[off] = Tn;
-                bad = bad || (out_lane && !(Tn - Tn == 0.0));
+                bad = bad || (out_lane && !__builtin_isfinite(Tn));
             }
         } else if (out_lane && e >= te.y0 && e < te.y0 + H && e >= 0 && e < d.nr) {
             double Tn;
@@ -1018,7 +1032,7 @@ __device__ __forceinline__ void thermal_strip_sp(cdesc &d, const PbTile &te, int
                 Tn = T0_4 + (double)((1.0f / 6.0f) * (acc_4 + h4));
             }
             Tout[(uint32_t)e * (uint32_t)d.pitch + (uint32_t)xg] = Tn;
-            bad = bad || !(Tn - Tn == 0.0);
+            bad = bad || !__builtin_isfinite(Tn);
         }
 
         // shift the windows by one row
