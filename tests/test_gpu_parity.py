@@ -228,6 +228,34 @@ def test_bottom_window_and_zero_steps():
     g.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_profiled_steps_are_the_same_steps(precision):
+    """pb_profile_steps runs real steps: stepping with HIP events around every
+    launch (events reserved ahead, then reused by a second, longer call that
+    creates the missing ones, with heat-flux samples inside) gives the same
+    bits and the same time as plain stepping, and positive launch times."""
+    P, d, bc, rho, T = pool_case(120, 60, 6, superheat=0.15, n_spots=3, seed=2)
+    a = gpu_domain(P, bc, rho, T, precision=precision)
+    b = gpu_domain(P, bc, rho, T, precision=precision)
+    for dom in (a, b):
+        dom.flux_window(1, 31, 3)
+    a.step(30)
+    b.profile_reserve(10)
+    p1 = b.profile_steps(10)
+    p2 = b.profile_steps(20)
+    assert a.t == b.t == 30
+    for p in (p1, p2):
+        assert p["flow_ms"] > 0 and p["thermal_ms"] > 0 and p["step_ms"] >= p["flow_ms"]
+    ra, rb = a.read(), b.read()
+    for k in ("rho", "ux", "uy", "T", "f"):
+        np.testing.assert_array_equal(ra[k], rb[k], err_msg=k)
+    fa, fb = a.heat_flux(), b.heat_flux()
+    assert fa["n_samples"] == fb["n_samples"] == 10
+    assert fa["q_bottom_mean"] == fb["q_bottom_mean"]
+    a.close()
+    b.close()
+
+
 def test_checkpoint_resume_fp64_bit_exact():
     """read f(t), T(t) and rho_bar, restore into a fresh domain, continue:
     identical to the uninterrupted run."""
