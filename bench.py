@@ -17,6 +17,7 @@ on a bounded sample of the same workload; beside them the serving legs
 single-domain set-ups.
 """
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -377,6 +378,15 @@ def serving_legs(log):
                                 within_3pct=int((dq <= 0.03).sum()))
     out["batched_tiles"] = dict(flow=list(tiles["tile"]), thermal=tiles["thermal_tile"],
                                 ms_per_step_curve_mix=round(tiles["ms_per_step"], 4))
+    # the same mix with the launches' grids capped (blocks loop over the work
+    # lists): 768 blocks hold every flow block the chip runs at once, 3072 one
+    # energy wavefront per SIMD slot; 0 = one block per tile
+    tuned = [dataclasses.replace(s, tile=tiles["tile"], thermal_tile=tiles["thermal_tile"]) for s in specs]
+    grid = {}
+    for pblocks in (0, 768, 3072):
+        grid[str(pblocks)] = round(autotune._time_batch(tuned, 300, 50, 100, persistent_blocks=pblocks), 4)
+        log(f"serving: curve mix, persistent grid {pblocks}: {grid[str(pblocks)]} ms/step")
+    out["batched_tiles"]["ms_per_step_by_persistent_grid"] = grid
     # Poisson stream: one job mix (arrival gaps drawn at 1 job/s), replayed at
     # 0.5, 0.8 and 1.2 x the FP32 capacity measured on the same jobs submitted
     # at once.  The resident set changes from chunk to chunk, so the batches

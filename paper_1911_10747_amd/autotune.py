@@ -76,11 +76,11 @@ def tune(nx, nyf, nys, precision=pb.PB_FP32_DEV, steps=30, warmup=5, use_cache=T
     return r
 
 
-def _time_batch(specs, steps, warmup, steps_per_graph):
+def _time_batch(specs, steps, warmup, steps_per_graph, persistent_blocks=0):
     import time
     doms = [presets.make_domain(s, with_window=False) for s in specs]
     try:
-        b = pb.Batch(doms, steps_per_graph=steps_per_graph)
+        b = pb.Batch(doms, steps_per_graph=steps_per_graph, persistent_blocks=persistent_blocks)
         try:
             b.step(warmup)
             for dm in doms:
