@@ -588,12 +588,18 @@ __device__ __forceinline__ RowIn load_row(cdesc &d, const double PB_GAS *Tin, co
 template <bool FL>
 __device__ __forceinline__ double apply9(const Coef9 &c, int kind, double Sc, double SR, double SL, double Nc,
                                          double NR, double NL, double Sc_, double SR_, double SL_) {
-    // rows: S* centre row, N* row above, *_ row below; order of Eq. 2
-    // three independent row sums keep the dependency chain short
-    const double rm = c.k0 * Sc + c.k1 * SR + c.k3 * SL;
-    const double ra = c.k2 * Nc + c.k5 * NR + c.k6 * NL;
-    const double rb = c.k4 * Sc_ + c.k7 * SL_ + c.k8 * SR_;
-    double K = rm + (ra + rb);
+    // rows: S* centre row, N* row above, *_ row below; order of Eq. 2.  One
+    // multiply-add chain, the centre and lower rows (known a row earlier)
+    // first, so the row above, computed last, enters through three of them
+    double K = c.k0 * Sc;
+    K = fma(c.k1, SR, K);
+    K = fma(c.k3, SL, K);
+    K = fma(c.k4, Sc_, K);
+    K = fma(c.k7, SL_, K);
+    K = fma(c.k8, SR_, K);
+    K = fma(c.k2, Nc, K);
+    K = fma(c.k5, NR, K);
+    K = fma(c.k6, NL, K);
     if (FL || kind == KIND_FLUID) K += c.beta * fsqrt(Sc);
     return K;
 }
