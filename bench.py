@@ -384,7 +384,7 @@ def serving_legs(log):
     tuned = [dataclasses.replace(s, tile=tiles["tile"], thermal_tile=tiles["thermal_tile"]) for s in specs]
     grid = {}
     for pblocks in (0, 768, 3072):
-        grid[str(pblocks)] = round(autotune._time_batch(tuned, 300, 50, 100, persistent_blocks=pblocks), 4)
+        grid[str(pblocks)] = round(autotune.time_batch(tuned, 300, 50, 100, persistent_blocks=pblocks), 4)
         log(f"serving: curve mix, persistent grid {pblocks}: {grid[str(pblocks)]} ms/step")
     out["batched_tiles"]["ms_per_step_by_persistent_grid"] = grid
     # Poisson stream: one job mix (arrival gaps drawn at 1 job/s), replayed at

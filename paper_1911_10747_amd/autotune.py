@@ -76,7 +76,10 @@ def tune(nx, nyf, nys, precision=pb.PB_FP32_DEV, steps=30, warmup=5, use_cache=T
     return r
 
 
-def _time_batch(specs, steps, warmup, steps_per_graph, persistent_blocks=0):
+def time_batch(specs, steps, warmup, steps_per_graph, persistent_blocks=0):
+    """Wall time per step (ms) of the domains of specs stepped as one batch:
+    warmup steps, then steps timed, graph replay of steps_per_graph; with
+    persistent_blocks > 0 the launches' grids are capped at that many blocks."""
     import time
     doms = [presets.make_domain(s, with_window=False) for s in specs]
     try:
@@ -111,13 +114,13 @@ def tune_batch(specs, steps=300, warmup=50, steps_per_graph=100, log=None):
 
     flow = {}
     for tile in FLOW_TILES:
-        flow[tile] = _time_batch(with_tiles(tile, 0), steps, warmup, steps_per_graph)
+        flow[tile] = time_batch(with_tiles(tile, 0), steps, warmup, steps_per_graph)
         if log:
             log(f"autotune batch of {len(specs)}: flow tile {tile}: {flow[tile]:.4f} ms/step")
     best_tile = min(flow, key=flow.get)
     therm = {}
     for v in THERMAL_VARIANTS:
-        therm[v] = _time_batch(with_tiles(best_tile, v), steps, warmup, steps_per_graph)
+        therm[v] = time_batch(with_tiles(best_tile, v), steps, warmup, steps_per_graph)
         if log:
             log(f"autotune batch of {len(specs)}: thermal variant {v}: {therm[v]:.4f} ms/step")
     best_v = min(therm, key=therm.get)
