@@ -63,6 +63,19 @@ __device__ __forceinline__ T PB_GAS *gcast_w(void *p) { return (T PB_GAS *)p; }
 
 __device__ __forceinline__ void flag_error(cdesc &d) { atomicOr(d.err, 1); }
 
+// The element at a 32-bit byte offset from a base that is the same for every
+// lane, written so that the access can take the base from scalar registers
+// and the offset from one vector register instead of a 64-bit address per
+// lane (the flow's stores compile so: 12 fewer vector instructions a node).
+template <typename V>
+__device__ __forceinline__ V at_byte(const V PB_GAS *base, uint32_t boff) {
+    return *(const V PB_GAS *)((const char PB_GAS *)base + boff);
+}
+template <typename V>
+__device__ __forceinline__ V PB_GAS *at_byte_w(V PB_GAS *base, uint32_t boff) {
+    return (V PB_GAS *)((char PB_GAS *)base + boff);
+}
+
 // reciprocal and square root from the hardware approximations refined by
 // Newton steps (within about one ulp of the correctly rounded values)
 __device__ __forceinline__ double frcp(double x) {
@@ -146,10 +159,13 @@ __device__ __forceinline__ void pull_inner(const FT PB_GAS *fin, const FT PB_GAS
 // can be in flight before that copy is complete.
 __device__ __forceinline__ void load_inner_raw(const float PB_GAS *fin, uint32_t plane, uint32_t pitch, uint32_t idx,
                                                float v[9]) {
+    // the base of plane i shifted by e_i is the same for every lane; each
+    // lane adds the 32-bit byte offset of its node
+    const uint32_t boff = idx * 4u;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const uint32_t src = idx - (uint32_t)(kEY[i] * (int)pitch) - (uint32_t)kEX[i];
-        v[i] = (fin + (uint32_t)i * plane)[src];
+        const float PB_GAS *b = fin + ((int64_t)i * plane - (int64_t)kEY[i] * pitch - kEX[i]);
+        v[i] = at_byte(b, boff);
     }
 }
 template <int RW>
@@ -181,12 +197,13 @@ struct GlobalStore {
     FT PB_GAS *vy;
     uint32_t plane, oidx;
     __device__ __forceinline__ void pop(int i, FT v) const {
-        __builtin_nontemporal_store(v, &(f + (uint32_t)i * plane)[oidx]);
+        __builtin_nontemporal_store(v, at_byte_w(f + (size_t)i * plane, oidx * (uint32_t)sizeof(FT)));
     }
     __device__ __forceinline__ void fields(double r, FT ux, FT uy) const {
-        __builtin_nontemporal_store((FT)r, &rho[oidx]);
-        __builtin_nontemporal_store(ux, &vx[oidx]);
-        __builtin_nontemporal_store(uy, &vy[oidx]);
+        const uint32_t boff = oidx * (uint32_t)sizeof(FT);
+        __builtin_nontemporal_store((FT)r, at_byte_w(rho, boff));
+        __builtin_nontemporal_store(ux, at_byte_w(vx, boff));
+        __builtin_nontemporal_store(uy, at_byte_w(vy, boff));
     }
 };
 
@@ -374,12 +391,12 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
         }
         float v[9], vh[9];
         load_inner_raw(fin, plane, pitch, idx, v);
-        const double Tn = Tt[toff + idx];
+        const double Tn = at_byte(Tt + toff, idx * 8u);
         const uint32_t hidx = (uint32_t)(te.y0 + ly - 1) * pitch + (uint32_t)(te.x0 + lx - 1);
         double Th = 0.0;
         if (has_h) {
             load_inner_raw(fin, plane, pitch, hidx, vh);
-            Th = Tt[toff + hidx];
+            Th = at_byte(Tt + toff, hidx * 8u);
         }
 #pragma unroll
         for (int u = 0; u < NQ; ++u) {
@@ -458,9 +475,11 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
     }
 }
 
+// 512-thread stepping blocks are held to 80 VGPRs, 6 waves per SIMD (three
+// blocks per CU)
 template <typename FT, int BX, int BY, int MODE>
-__global__ __launch_bounds__(BX *BY) void k_flow(const PbDesc *const *__restrict__ dps,
-                                                  const PbTile *__restrict__ tiles, int ntiles, int k) {
+__global__ __launch_bounds__(BX *BY, (BX * BY == 512 && MODE == PB_MODE_STEP ? 6 : 1))
+void k_flow(const PbDesc *const *__restrict__ dps, const PbTile *__restrict__ tiles, int ntiles, int k) {
     constexpr int LW = BX + 2, LH = BY + 2;
     static_assert(2 * LW + 2 * BY <= BX * BY, "halo larger than block");
     __shared__ double s_psi[LW * LH];
