@@ -474,7 +474,13 @@ def main():
                            precision=prec, tile=(tx, ty), thermal_tile=thermal_tile)
     dom = presets.make_domain(spec)
     dom.flux_window(0, 1 << 62, 10)
-    print(f"bench: {args.workload} {nx}x{nyf}+{nys} prec={prec}: warmup {args.warmup}", file=sys.stderr, flush=True)
+    # untimed steps until 50 ms of GPU work have run, so that the clocks have
+    # ramped up from the idle of the set-up before the warmup and the timed
+    # steps (a short timed run would otherwise measure the ramp)
+    from paper_1911_10747_amd import autotune as _at
+    settle_steps = _at.settle(dom.step, dom.sync)
+    print(f"bench: {args.workload} {nx}x{nyf}+{nys} prec={prec}: {settle_steps} settle steps, warmup {args.warmup}",
+          file=sys.stderr, flush=True)
     dom.step(args.warmup)
     dom.profile_reserve(args.steps)     # the timed steps' HIP events, created before the clock starts
     dom.sync()
@@ -500,6 +506,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "settle_steps": settle_steps,
         "ms_per_step": round(ms_step, 4),
         "higher_is_better": True,
         "scaling": "weak",

@@ -38,8 +38,26 @@ def save_cache(c):
     os.replace(tmp, CACHE)
 
 
+def settle(step, sync, min_s=0.05, chunk=20):
+    """Untimed steps (step(chunk), then sync()) until min_s of wall time has
+    passed with the GPU busy, and return how many ran.  The GPU's clocks ramp
+    up over some 30 ms after an idle spell such as a domain's set-up: on
+    4096x2048+64 the first 20 steps after 2 s of idle ran at 195/81 us
+    (flow/energy launch) against 181/66 us from about 120 steps on, so a
+    timing taken right after set-up measures the ramp."""
+    import time
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < min_s:
+        step(chunk)
+        sync()
+        n += chunk
+    return n
+
+
 def _time(spec, steps, warmup):
     dom = presets.make_domain(spec, with_window=False)
+    settle(dom.step, dom.sync)
     dom.step(warmup)
     prof = dom.profile_steps(steps)
     dom.close()
@@ -85,6 +103,7 @@ def time_batch(specs, steps, warmup, steps_per_graph, persistent_blocks=0):
     try:
         b = pb.Batch(doms, steps_per_graph=steps_per_graph, persistent_blocks=persistent_blocks)
         try:
+            settle(b.step, lambda: [dm.sync() for dm in doms])
             b.step(warmup)
             for dm in doms:
                 dm.sync()
