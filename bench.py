@@ -284,7 +284,7 @@ def small_configs(log):
     hot spots, superheat 0.1 Tc.  (The oracle's rate on the 100x100 pool is in
     the cpu_baseline leg.)  Each is timed with plain launches and as a batch of
     one replayed from captured graphs of 100 steps."""
-    from paper_1911_10747_amd import poolboil as pb, presets
+    from paper_1911_10747_amd import autotune, poolboil as pb, presets
     out = {}
     for name, nx, nyf, nys, prec, spc, steps in (("pool_100x100+10_fp64", 100, 100, 10, 0, 25, 4000),
                                                  ("pool_400x400+20_fp32dev", 400, 400, 20, 1, 67, 4000),
@@ -296,6 +296,7 @@ def small_configs(log):
             dom = presets.make_domain(spec, with_window=False)
             b = pb.Batch([dom], steps_per_graph=100) if graph else None
             stepper = b if graph else dom
+            autotune.settle(stepper.step, dom.sync)
             stepper.step(200)
             dom.sync()
             t0 = time.perf_counter()
