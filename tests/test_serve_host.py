@@ -109,3 +109,26 @@ def test_latency_percentiles():
     rs = [serve.JobResult(job_id=i, arrival=0.0, finish=float(i + 1)) for i in range(100)]
     st = serve.latency_stats(rs)
     assert st["n"] == 100 and st["p50_s"] == pytest.approx(50.5) and st["p99_s"] == pytest.approx(99.01)
+
+
+def test_settle_steps_until_the_time_has_passed():
+    """autotune.settle runs whole chunks, syncing after each, until min_s of
+    wall time has passed, and returns the steps it ran."""
+    import time
+    from paper_1911_10747_amd import autotune
+    calls = []
+
+    def step(n):
+        calls.append(("step", n))
+        time.sleep(0.004)
+
+    def sync():
+        calls.append(("sync", 0))
+
+    t0 = time.perf_counter()
+    n = autotune.settle(step, sync, min_s=0.02, chunk=7)
+    assert time.perf_counter() - t0 >= 0.02
+    steps = [c for c in calls if c[0] == "step"]
+    assert n == 7 * len(steps) and len(steps) >= 2
+    assert calls[0][0] == "step" and calls[-1][0] == "sync"
+    assert all(a[0] == "step" and b[0] == "sync" for a, b in zip(calls[::2], calls[1::2]))
