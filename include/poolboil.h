@@ -189,8 +189,8 @@ int pb_read_fields(pb_domain *dom, double *rho, double *ux, double *uy, double *
  * the same outputs, bit for bit, but the FP64 read-back staging is a fixed
  * device array of PB_READ_NOALLOC_MAX_BYTES that every GPU the library runs
  * on holds for the life of the process, instead of memory allocated on the
- * first read.  The domain needs 12 * ny_fluid * pitch * 8 bytes of it (pitch =
- * nx rounded up to 64, so ny_fluid * pitch <= 699050); a larger domain gets
+ * first read.  The domain needs (13 * ny_fluid + ny_solid) * nx * 8 bytes of
+ * it (so (13 * ny_fluid + ny_solid) * nx <= 8388608); a larger domain gets
  * PB_EINVAL before any device work.  No hipMalloc/hipFree is called.  Every
  * call on a GPU shares that GPU's array, which keeps the last call's
  * contents: calls that overlap on one GPU (other threads or streams) race.

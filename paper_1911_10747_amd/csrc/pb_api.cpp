@@ -350,17 +350,44 @@ double bc_bottom(const pb_domain *d, int x, int64_t t) {
     return d->Tb.empty() ? d->hd.T_top : d->Tb[x];
 }
 
-int copy_rows_h2d(pb_domain *d, void *dst, const double *src, int rows) {
-    PB_HIP(hipMemcpy2DAsync(dst, (size_t)d->pitch * 8, src, (size_t)d->cfg.nx * 8, (size_t)d->cfg.nx * 8, rows,
-                            hipMemcpyHostToDevice, d->stream));
+// Host arrays hold dense rows of nx elements, device arrays rows pitch
+// elements apart.  Every host transfer is one contiguous copy (a 2D copy
+// between pageable host memory and the device moves row by row, minutes for
+// a tall, narrow domain); where pitch != nx the rows are re-pitched on the
+// device through tmp (rows x nx elements; unused when pitch == nx).
+int upload_rows(pb_domain *d, void *dst, const void *src, int rows, int elem, void *tmp) {
+    const size_t nx = (size_t)d->cfg.nx, bytes = (size_t)rows * nx * elem;
+    if ((size_t)d->pitch == nx) {
+        PB_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, d->stream));
+        return PB_OK;
+    }
+    PB_HIP(hipMemcpyAsync(tmp, src, bytes, hipMemcpyHostToDevice, d->stream));
+    PB_HIP(pb_launch_repitch(elem, dst, (size_t)d->pitch, tmp, nx, nx, (size_t)rows, d->stream));
     return PB_OK;
 }
 
-int copy_rows_d2h(pb_domain *d, double *dst, const void *src, int rows) {
-    PB_HIP(hipMemcpy2DAsync(dst, (size_t)d->cfg.nx * 8, src, (size_t)d->pitch * 8, (size_t)d->cfg.nx * 8, rows,
-                            hipMemcpyDeviceToHost, d->stream));
+int download_rows(pb_domain *d, double *dst, const double *src, int rows, double *tmp) {
+    const size_t nx = (size_t)d->cfg.nx, bytes = (size_t)rows * nx * sizeof(double);
+    if ((size_t)d->pitch != nx) {
+        PB_HIP(pb_launch_repitch(8, tmp, nx, src, (size_t)d->pitch, nx, (size_t)rows, d->stream));
+        src = tmp;
+    }
+    PB_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, d->stream));
     return PB_OK;
 }
+
+// Device memory for the dense rows of an upload (rows x nx doubles), freed
+// when it goes out of scope; none when pitch == nx.
+struct UploadTmp {
+    void *p = nullptr;
+    ~UploadTmp() {
+        if (p) (void)hipFree(p);
+    }
+    bool get(const pb_domain *d, int rows) {
+        if (d->pitch == d->cfg.nx) return true;
+        return hipMalloc(&p, (size_t)rows * d->cfg.nx * sizeof(double)) == hipSuccess;
+    }
+};
 
 int check_dom(const pb_domain *d) {
     if (!d) return fail(PB_EINVAL, "domain is NULL");
@@ -526,6 +553,13 @@ int pb_create_domain(const pb_config *cfg, void *stream, void *dev_mem, size_t d
     h.rho_S = cfg->rho_S;
     h.C_S = cfg->C_S;
     h.lambda_S = cfg->lambda_S;
+    h.eos_s0 = 1.0 + h.kappa;
+    h.eos_s1 = h.kappa * h.inv_sqrtTc;
+    h.two_invG = 2.0 * h.invG;
+    h.cw_k = 12.0 * cfg->varpi * cfg->s_e;
+    h.hse = 1.0 - 0.5 * cfg->s_e;
+    h.hsq = 1.0 - 0.5 * cfg->s_q;
+    h.s2sign = (cfg->flags & PB_SBAR2_PLUS) ? 1.0 : -1.0;
     d->ddesc = (PbDesc *)(d->base + L.desc);
     d->dptr = (PbDesc **)(d->base + L.dptr);
     d->dtiles_flow = (PbTile *)(d->base + L.tflow);
@@ -594,18 +628,21 @@ int pb_set_fields(pb_domain *d, const double *rho, const double *T) {
     std::vector<double> Th(T, T + (size_t)nx * d->nr);
     if (!(d->cfg.flags & PB_PERIODIC_Y))
         for (int x = 0; x < nx; ++x) Th[x] = bc_bottom(d, x, 0);
+    UploadTmp tmp;
+    if (!tmp.get(d, d->nr)) return fail(PB_ENOMEM, "upload staging allocation failed");
     PB_HIP(hipStreamSynchronize(d->stream));
     d->t = 0;
     d->par = 0;
     d->hd.rho_bar = sum / ((double)nx * nyf);
-    // the FP64 densities go through T[1] (nr >= nyf rows of the same pitch),
-    // which k_init reads before T is uploaded behind it on the same stream
-    if ((rc = copy_rows_h2d(d, d->hd.T[1], rho, nyf))) return rc;
+    // the FP64 densities go through T[1] as dense rows (nr >= nyf rows of
+    // pitch >= nx), which k_init reads before T is uploaded behind it on the
+    // same stream
+    PB_HIP(hipMemcpyAsync(d->hd.T[1], rho, (size_t)nyf * nx * sizeof(double), hipMemcpyHostToDevice, d->stream));
     PB_HIP(hipMemsetAsync(d->hd.err, 0, sizeof(int32_t), d->stream));
     if ((rc = upload_desc(d))) return rc;
     PB_HIP(pb_launch_init(d->cfg.precision, d->ddesc, d->hd.T[1], d->stream));
     for (int b = 0; b < 2; ++b)
-        if ((rc = copy_rows_h2d(d, d->hd.T[b], Th.data(), d->nr))) return rc;
+        if ((rc = upload_rows(d, d->hd.T[b], Th.data(), d->nr, 8, tmp.p))) return rc;
     PB_HIP(hipStreamSynchronize(d->stream));
     d->fields_set = true;
     return PB_OK;
@@ -639,14 +676,16 @@ int pb_set_fields_full(pb_domain *d, const double *f, const double *T, int64_t t
         for (int i = 0; i < 9; ++i) s += fs[(size_t)i * np + n];
         rref[n] = s;
     }
+    UploadTmp tmp;
+    if (!tmp.get(d, d->nr)) return fail(PB_ENOMEM, "upload staging allocation failed");
     PB_HIP(hipStreamSynchronize(d->stream));
     const int par = 0;
     if (d->cfg.precision == PB_FP64) {
         for (int i = 0; i < 9; ++i)
-            if ((rc = copy_rows_h2d(d, (double *)d->hd.f[par] + (size_t)i * nyf * d->pitch, fs.data() + (size_t)i * np,
-                                    nyf)))
+            if ((rc = upload_rows(d, (double *)d->hd.f[par] + (size_t)i * nyf * d->pitch, fs.data() + (size_t)i * np,
+                                  nyf, 8, tmp.p)))
                 return rc;
-        if ((rc = copy_rows_h2d(d, d->hd.rho[par], rref.data(), nyf))) return rc;
+        if ((rc = upload_rows(d, d->hd.rho[par], rref.data(), nyf, 8, tmp.p))) return rc;
     } else {
         // deviations against the density as stored (FP32)
         std::vector<float> dev(9 * np), r32(np);
@@ -655,15 +694,14 @@ int pb_set_fields_full(pb_domain *d, const double *f, const double *T, int64_t t
             for (size_t n = 0; n < np; ++n)
                 dev[(size_t)i * np + n] = (float)(fs[(size_t)i * np + n] - kWh[i] * (double)r32[n]);
         for (int i = 0; i < 9; ++i)
-            PB_HIP(hipMemcpy2DAsync((float *)d->hd.f[par] + (size_t)i * nyf * d->pitch, (size_t)d->pitch * 4,
-                                    dev.data() + (size_t)i * np, (size_t)nx * 4, (size_t)nx * 4, nyf,
-                                    hipMemcpyHostToDevice, d->stream));
-        PB_HIP(hipMemcpy2DAsync(d->hd.rho[par], (size_t)d->pitch * 4, r32.data(), (size_t)nx * 4, (size_t)nx * 4, nyf,
-                                hipMemcpyHostToDevice, d->stream));
+            if ((rc = upload_rows(d, (float *)d->hd.f[par] + (size_t)i * nyf * d->pitch, dev.data() + (size_t)i * np,
+                                  nyf, 4, tmp.p)))
+                return rc;
+        if ((rc = upload_rows(d, d->hd.rho[par], r32.data(), nyf, 4, tmp.p))) return rc;
         PB_HIP(hipStreamSynchronize(d->stream));
     }
     for (int b = 0; b < 2; ++b)
-        if ((rc = copy_rows_h2d(d, d->hd.T[b], T, d->nr))) return rc;
+        if ((rc = upload_rows(d, d->hd.T[b], T, d->nr, 8, tmp.p))) return rc;
     PB_HIP(hipMemsetAsync(d->hd.err, 0, sizeof(int32_t), d->stream));
     d->t = t;
     d->par = par;
@@ -696,31 +734,36 @@ int pb_sync(pb_domain *d) {
 
 namespace {
 
-// Read-back through FP64 staging planes at `stage` (12 x ny_fluid x pitch
-// doubles: f, rho, v_x, v_y): the flow kernel in read mode rebuilds f(t) and
-// forms rho(t), v(t) there, then the planes are copied to the host.
+// Doubles of read-back staging a domain needs: 12 dense [ny_fluid][nx]
+// planes and T's nr = ny_fluid + ny_solid dense rows.
+size_t read_stage_doubles(const pb_domain *d) {
+    return (12 * (size_t)d->cfg.ny_fluid + (size_t)d->nr) * (size_t)d->cfg.nx;
+}
+
+// Read-back through FP64 staging at `stage` (read_stage_doubles(d)): dense
+// [ny_fluid][nx] planes f_0..f_8, rho, v_x, v_y, which the flow kernel in
+// read mode fills with f(t) rebuilt and rho(t), v(t), then T(t) re-pitched
+// into dense rows behind them; each field goes to the host in one copy.
 int read_through(pb_domain *d, double *stage, double *rho, double *ux, double *uy, double *T, double *f) {
     const int nyf = d->cfg.ny_fluid;
-    const size_t nf = (size_t)nyf * d->pitch;
+    const size_t nfd = (size_t)nyf * d->cfg.nx, bytes = nfd * sizeof(double);
     int rc;
     if (d->hd.rd_f != stage) {
         d->hd.rd_f = stage;
-        d->hd.rd_rho = stage + 9 * nf;
-        d->hd.rd_vx = stage + 10 * nf;
-        d->hd.rd_vy = stage + 11 * nf;
+        d->hd.rd_rho = stage + 9 * nfd;
+        d->hd.rd_vx = stage + 10 * nfd;
+        d->hd.rd_vy = stage + 11 * nfd;
         if ((rc = upload_desc(d))) return rc;
     }
     if (rho || ux || uy || f) {
         PB_HIP(pb_launch_flow(d->cfg.precision, PB_MODE_READ, d->fvar, (const PbDesc *const *)d->dptr, d->dtiles_flow,
                               d->nt_flow, d->nt_flow, 0, d->stream));
     }
-    if (rho && (rc = copy_rows_d2h(d, rho, d->hd.rd_rho, nyf))) return rc;
-    if (ux && (rc = copy_rows_d2h(d, ux, d->hd.rd_vx, nyf))) return rc;
-    if (uy && (rc = copy_rows_d2h(d, uy, d->hd.rd_vy, nyf))) return rc;
-    if (T && (rc = copy_rows_d2h(d, T, d->hd.T[d->par], d->nr))) return rc;
-    if (f)
-        for (int i = 0; i < 9; ++i)
-            if ((rc = copy_rows_d2h(d, f + (size_t)i * nyf * d->cfg.nx, d->hd.rd_f + (size_t)i * nf, nyf))) return rc;
+    if (rho) PB_HIP(hipMemcpyAsync(rho, d->hd.rd_rho, bytes, hipMemcpyDeviceToHost, d->stream));
+    if (ux) PB_HIP(hipMemcpyAsync(ux, d->hd.rd_vx, bytes, hipMemcpyDeviceToHost, d->stream));
+    if (uy) PB_HIP(hipMemcpyAsync(uy, d->hd.rd_vy, bytes, hipMemcpyDeviceToHost, d->stream));
+    if (T && (rc = download_rows(d, T, d->hd.T[d->par], d->nr, stage + 12 * nfd))) return rc;
+    if (f) PB_HIP(hipMemcpyAsync(f, d->hd.rd_f, 9 * bytes, hipMemcpyDeviceToHost, d->stream));
     PB_HIP(hipStreamSynchronize(d->stream));
     return PB_OK;
 }
@@ -733,9 +776,8 @@ int pb_read_fields(pb_domain *d, double *rho, double *ux, double *uy, double *T,
     int rc = check_dom(d);
     if (rc) return rc;
     if (!d->fields_set) return fail(PB_ESTATE, "pb_set_fields was not called");
-    const size_t nf = (size_t)d->cfg.ny_fluid * d->pitch;
     PB_HIP(hipStreamSynchronize(d->stream));
-    if (!d->rd && hipMalloc((void **)&d->rd, 12 * nf * sizeof(double)) != hipSuccess)
+    if (!d->rd && hipMalloc((void **)&d->rd, read_stage_doubles(d) * sizeof(double)) != hipSuccess)
         return fail(PB_ENOMEM, "read staging allocation failed");
     return read_through(d, d->rd, rho, ux, uy, T, f);
 }
@@ -744,10 +786,11 @@ int pb_read_fields_noalloc(pb_domain *d, double *rho, double *ux, double *uy, do
     int rc = check_dom(d);
     if (rc) return rc;
     if (!d->fields_set) return fail(PB_ESTATE, "pb_set_fields was not called");
-    const size_t need = 12 * (size_t)d->cfg.ny_fluid * d->pitch * sizeof(double);
+    const size_t need = read_stage_doubles(d) * sizeof(double);
     if (need > PB_SCRATCH_BYTES)
-        return fail(PB_EINVAL, "read-back staging of %zu bytes exceeds the fixed %zu bytes (ny_fluid * pitch <= %zu)",
-                    need, (size_t)PB_SCRATCH_BYTES, (size_t)PB_SCRATCH_BYTES / (12 * sizeof(double)));
+        return fail(PB_EINVAL,
+                    "read-back staging of %zu bytes exceeds the fixed %zu bytes ((13 * ny_fluid + ny_solid) * nx <= %zu)",
+                    need, (size_t)PB_SCRATCH_BYTES, (size_t)PB_SCRATCH_BYTES / sizeof(double));
     int cur = 0;
     PB_HIP(hipGetDevice(&cur));
     if (cur != d->device) PB_HIP(hipSetDevice(d->device));

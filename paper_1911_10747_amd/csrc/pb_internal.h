@@ -39,6 +39,12 @@ struct PbDesc {
     double tau_V, rho_V, ktau;   // tau(rho) = tau_V + (rho - rho_V) * ktau  (Eq. 5)
     double g, rho_bar;
     double Cv, Cvchi, rho_S, C_S, lambda_S;
+    // uniform factors of the flow update, derived once from the constants above
+    double eos_s0, eos_s1;   // s(T) = 1 + kappa (1 - sqrt(T / Tc)) = eos_s0 - eos_s1 sqrt(T)  (Eq. 13)
+    double two_invG;         // 2 / G  (Eq. 12)
+    double cw_k;             // 12 varpi s_e  (varpi term of Eq. 9)
+    double hse, hsq;         // 1 - s_e / 2, 1 - s_q / 2  (Eq. 7)
+    double s2sign;           // +1 with PB_SBAR2_PLUS (row 2 adds the varpi term), else -1
 };
 
 struct PbTile {
@@ -58,6 +64,10 @@ hipError_t pb_launch_thermal(int prec, int tile_variant, const PbDesc *const *d_
 hipError_t pb_launch_flux(int prec, const PbDesc *const *d_descs, int ndom, int k, hipStream_t s);
 hipError_t pb_launch_advance(PbDesc *const *d_descs, int ndom, int nsteps, hipStream_t s);
 hipError_t pb_launch_init(int prec, const PbDesc *d_desc, const double *rho_src, hipStream_t s);
+// 2D copy on the device: rows x width elements of elem_bytes (4 or 8) from
+// rows spitch elements apart to rows dpitch elements apart
+hipError_t pb_launch_repitch(int elem_bytes, void *dst, size_t dpitch, const void *src, size_t spitch, size_t width,
+                             size_t rows, hipStream_t s);
 
 // Fixed read-back staging of pb_read_fields_noalloc: a file-scope device array
 // of PB_SCRATCH_BYTES in pb_kernels.hip, one per GPU for the life of the

@@ -24,6 +24,7 @@
 // (so the FP64 rebuild on load is exact up to the rounding of the deviation),
 // and runs the energy equation in FP32 increments over FP64 T (see the FP32
 // sweep below).
+#include <algorithm>
 #include <mutex>
 #include <type_traits>
 
@@ -42,7 +43,7 @@ __device__ constexpr double kW[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9
 __device__ constexpr double kWF[9] = {0.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0,
                                       1.0 / 12.0, 1.0 / 12.0, 1.0 / 12.0, 1.0 / 12.0};
 
-constexpr uint32_t F_PERY = 0x1u, F_FROZEN = 0x4u, F_S2PLUS = 0x8u, F_FMONLY = 0x10u;
+constexpr uint32_t F_PERY = 0x1u, F_FROZEN = 0x4u, F_FMONLY = 0x10u;
 
 __device__ __forceinline__ int wrap_once(int v, int n) {
     v += (v < 0) ? n : 0;
@@ -98,12 +99,11 @@ __device__ __forceinline__ double fsqrt(double x) {
 // Eq. 13 and Eq. 12 (c = 1, c_s^2 = 1/3) with a single division; sets bad on a
 // negative radicand.
 __device__ __forceinline__ double eos_psi(cdesc &d, double rho, double T, bool &bad) {
-    const double st = fsqrt(T) * d.inv_sqrtTc;          // sqrt(T / Tc)
-    const double s = 1.0 + d.kappa * (1.0 - st);
+    const double s = d.eos_s0 - d.eos_s1 * fsqrt(T);    // 1 + kappa (1 - sqrt(T / Tc))
     const double br = d.b * rho;
     const double den1 = 1.0 - br, den2 = 1.0 + 2.0 * br - br * br;
     const double P = (rho * d.R * T * den2 - d.a * (s * s) * rho * rho * den1) * frcp(den1 * den2);
-    const double rad = 2.0 * (P - rho * (1.0 / 3.0)) * d.invG;
+    const double rad = (P - rho * (1.0 / 3.0)) * d.two_invG;
     bad = bad || !(rad >= 0.0);
     return fsqrt(rad);
 }
@@ -178,16 +178,6 @@ __device__ __forceinline__ void decode_lds(const float *s_rho, int lx, int ly, c
     for (int i = 0; i < 9; ++i) f[i] = kW[i] * (double)s_rho[(ly - kEY[i]) * RW + lx - kEX[i]] + (double)v[i];
 }
 
-// FP32 storage keeps f* - w_i rho_ref (the deviation) with rho_ref = rho(t)
-// rounded to FP32, the density stored beside it; FP64 storage f* itself
-template <typename FT>
-__device__ __forceinline__ FT encode_pop(int i, double fs, double rho_ref) {
-    if constexpr (std::is_same<FT, float>::value)
-        return (float)(fs - kW[i] * rho_ref);
-    else
-        return fs;
-}
-
 // Where a node's outputs go: global pointers at element offset oidx.  The
 // stores are non-temporal: the next reader is the next launch, after the whole
 // domain has streamed through L2, so keeping them out of L2 leaves it to the
@@ -219,26 +209,38 @@ struct GlobalStore {
 struct Mom {
     double rho, jx, jy, m1, m2, m4, m6, m7, m8;
 };
+// rho = sum of the f_i in one fixed grouping, used wherever a density is
+// summed from pulled populations (a node's own tile and the tiles that hold
+// it in their psi ring must get the same bits)
+__device__ __forceinline__ double node_rho(const double f[9]) {
+    return f[0] + (((f[1] + f[3]) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8])));
+}
 __device__ __forceinline__ Mom node_moments(const double f[9]) {
+    // the rows of M from shared partial sums (e_1..e_8 = E, N, W, S, NE, NW,
+    // SW, SE): a = f1 - f3, b = f2 - f4, c = f5 - f7, e = f6 - f8
+    const double a = f[1] - f[3], b = f[2] - f[4], c = f[5] - f[7], e = f[6] - f[8];
+    const double sa = (f[1] + f[3]) + (f[2] + f[4]), sd = (f[5] + f[7]) + (f[6] + f[8]);
+    const double cme = c - e, cpe = c + e;
     Mom m;
-    m.rho = 0.0;
-    m.jx = 0.0;
-    m.jy = 0.0;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        m.rho += f[i];
-        m.jx += kEX[i] * f[i];
-        m.jy += kEY[i] * f[i];
-    }
-    const double sa = f[1] + f[2] + f[3] + f[4];
-    const double sd = f[5] + f[6] + f[7] + f[8];
+    m.rho = node_rho(f);
+    m.jx = a + cme;                       // f1 - f3 + f5 - f6 - f7 + f8
+    m.jy = b + cpe;                       // f2 - f4 + f5 + f6 - f7 - f8
     m.m1 = -4.0 * f[0] - sa + 2.0 * sd;
     m.m2 = 4.0 * f[0] - 2.0 * sa + sd;
-    m.m4 = -2.0 * f[1] + 2.0 * f[3] + f[5] - f[6] - f[7] + f[8];
-    m.m6 = -2.0 * f[2] + 2.0 * f[4] + f[5] + f[6] - f[7] - f[8];
-    m.m7 = f[1] - f[2] + f[3] - f[4];
-    m.m8 = f[5] - f[6] + f[7] - f[8];
+    m.m4 = -2.0 * a + cme;
+    m.m6 = -2.0 * b + cpe;
+    m.m7 = (f[1] + f[3]) - (f[2] + f[4]);
+    m.m8 = (f[5] + f[7]) - (f[6] + f[8]);
     return m;
+}
+
+// sum over i = 1..8 of w(|e_i|^2) e_i p_i (Eqs. 11 and 14) from the
+// differences of opposite neighbours: (1/3)(p1 - p3, p2 - p4) plus
+// (1/12)(c - e, c + e) with c = p5 - p7, e = p6 - p8
+__device__ __forceinline__ void weighted_sum(const double p[9], double &sx, double &sy) {
+    const double c = p[5] - p[7], e = p[6] - p[8];
+    sx = kWF[1] * (p[1] - p[3]) + kWF[5] * (c - e);
+    sy = kWF[2] * (p[2] - p[4]) + kWF[5] * (c + e);
 }
 
 // Forces, velocity and collision of one fluid node from the moments mo of its
@@ -255,23 +257,25 @@ __device__ __forceinline__ bool node_update(cdesc &d, const double f[9], const M
                                             const GlobalStore<FT> &st) {
     const double rho = mo.rho, jx = mo.jx, jy = mo.jy;
     const bool frozen = (d.flags & F_FROZEN) != 0;
-    const uint32_t plane = (uint32_t)d.nyf * (uint32_t)d.pitch;
-    // Eq. 11 over fluid neighbours, Eq. 14 over wall neighbours
-    double sfx = 0.0, sfy = 0.0, sax = 0.0, say = 0.0;
+    // Eq. 11 over fluid neighbours (a wall neighbour's psi counts as 0), Eq. 14
+    // over wall neighbours (gw is 0 off the walls)
+    double pf[9];
 #pragma unroll
-    for (int i = 1; i < 9; ++i) {
-        if (!((wmask >> i) & 1u)) {
-            sfx += kWF[i] * kEX[i] * pn[i];
-            sfy += kWF[i] * kEY[i] * pn[i];
-        } else {
-            sax += kWF[i] * kEX[i] * gw[i];
-            say += kWF[i] * kEY[i] * gw[i];
-        }
-    }
+    for (int i = 1; i < 9; ++i) pf[i] = ((wmask >> i) & 1u) ? 0.0 : pn[i];
+    double sfx, sfy, sax, say;
+    weighted_sum(pf, sfx, sfy);
     const double Fmx = -d.G * psi * sfx, Fmy = -d.G * psi * sfy;
-    const double Fax = -psi * sax, Fay = -psi * say;
-    const double Fx = Fmx + Fax;
-    const double Fy = Fmy + Fay - (rho - d.rho_bar) * d.g;       // Eq. 15
+    // a node with no wall neighbour (every node of an inner tile) has F_ads = 0
+    // and skips it
+    const bool walls = wmask != 0u;
+    double Fsx = Fmx, Fsy = Fmy;            // F_m + F_ads
+    if (walls) {
+        weighted_sum(gw, sax, say);
+        Fsx = Fmx - psi * sax;
+        Fsy = Fmy - psi * say;
+    }
+    const double Fx = Fsx;
+    const double Fy = Fsy - (rho - d.rho_bar) * d.g;       // Eq. 15
     // 1/rho, 1/psi^2 and s_nu = 1/tau(rho) (Eq. 5) from one reciprocal of
     // their product (batch inversion)
     const double psi2 = psi * psi, tau = d.tau_V + (rho - d.rho_V) * d.ktau;
@@ -285,12 +289,16 @@ __device__ __forceinline__ bool node_update(cdesc &d, const double f[9], const M
     if (frozen) { vx = 0.0; vy = 0.0; }
 
     if constexpr (MODE == PB_MODE_READ) {
+        // the read-back staging holds dense rows ([nyf][nx] per field), so the
+        // host copies it out in one contiguous piece per field
+        const uint32_t y = oidx / (uint32_t)d.pitch, x = oidx - y * (uint32_t)d.pitch;
+        const uint32_t didx = y * (uint32_t)d.nx + x, dplane = (uint32_t)d.nyf * (uint32_t)d.nx;
         double PB_GAS *rdf = gcast_w<double>(d.rd_f);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) (rdf + (uint32_t)i * plane)[oidx] = f[i];
-        gcast_w<double>(d.rd_rho)[oidx] = rho;
-        gcast_w<double>(d.rd_vx)[oidx] = vx;
-        gcast_w<double>(d.rd_vy)[oidx] = vy;
+        for (int i = 0; i < 9; ++i) (rdf + (uint32_t)i * dplane)[didx] = f[i];
+        gcast_w<double>(d.rd_rho)[didx] = rho;
+        gcast_w<double>(d.rd_vx)[didx] = vx;
+        gcast_w<double>(d.rd_vy)[didx] = vy;
     } else {
         const double m1 = mo.m1, m2 = mo.m2, m4 = mo.m4, m6 = mo.m6, m7 = mo.m7, m8 = mo.m8;
         // equilibria (Eq. 6) with u = v of Eq. 10
@@ -300,36 +308,48 @@ __device__ __forceinline__ bool node_update(cdesc &d, const double f[9], const M
         const double meq7 = rho * (vx * vx - vy * vy), meq8 = rho * vx * vy;
         // forcing of Eq. 9; the varpi term times (1 - s_e/2) equals
         // 12 varpi s_e |F|^2 / psi^2 because tau_e = 1/s_e
-        const double Fwx = (d.flags & F_FMONLY) ? Fmx : Fmx + Fax;
-        const double Fwy = (d.flags & F_FMONLY) ? Fmy : Fmy + Fay;
+        const double Fwx = (d.flags & F_FMONLY) ? Fmx : Fsx;
+        const double Fwy = (d.flags & F_FMONLY) ? Fmy : Fsy;
         const double uF = vx * Fx + vy * Fy;
-        const double cw = 12.0 * d.varpi * d.s_e * (Fwx * Fwx + Fwy * Fwy) * inv_psi2;
-        const double cw2 = (d.flags & F_S2PLUS) ? cw : -cw;
+        const double cw = d.cw_k * (Fwx * Fwx + Fwy * Fwy) * inv_psi2;
+        const double cw2 = d.s2sign * cw;
         const double se = d.s_e, sq = d.s_q;
-        const double ms1 = m1 - se * (m1 - meq1) + (1.0 - 0.5 * se) * (6.0 * uF) + cw;
-        const double ms2 = m2 - se * (m2 - meq2) + (1.0 - 0.5 * se) * (-6.0 * uF) + cw2;
+        const double ms1 = m1 - se * (m1 - meq1) + d.hse * (6.0 * uF) + cw;
+        const double ms2 = m2 - se * (m2 - meq2) + d.hse * (-6.0 * uF) + cw2;
         const double ms3 = jx + Fx;                       // s_j drops out (Eq. 7 + Eq. 10)
-        const double ms4 = m4 - sq * (m4 - meq4) + (1.0 - 0.5 * sq) * (-Fx);
+        const double ms4 = m4 - sq * (m4 - meq4) + d.hsq * (-Fx);
         const double ms5 = jy + Fy;
-        const double ms6 = m6 - sq * (m6 - meq6) + (1.0 - 0.5 * sq) * (-Fy);
+        const double ms6 = m6 - sq * (m6 - meq6) + d.hsq * (-Fy);
         const double ms7 = m7 - snu * (m7 - meq7) + (1.0 - 0.5 * snu) * (2.0 * (vx * Fx - vy * Fy));
         const double ms8 = m8 - snu * (m8 - meq8) + (1.0 - 0.5 * snu) * (vx * Fy + vy * Fx);
         // f* = M^{-1} m*, M^{-1} = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
         const double a0 = rho * (1.0 / 9.0), a1 = ms1 * (1.0 / 36.0), a2 = ms2 * (1.0 / 36.0);
         const double a3 = ms3 * (1.0 / 6.0), a4 = ms4 * (1.0 / 12.0), a5 = ms5 * (1.0 / 6.0);
         const double a6 = ms6 * (1.0 / 12.0), a7 = ms7 * 0.25, a8 = ms8 * 0.25;
-        const double c0 = a0 - a1 - 2.0 * a2;       // axis-common part
-        const double cd = a0 + 2.0 * a1 + a2;       // diagonal-common part
-        const double rref = (double)(FT)rho;        // the density as stored
-        st.pop(0, encode_pop<FT>(0, a0 - 4.0 * a1 + 4.0 * a2, rref));
-        st.pop(1, encode_pop<FT>(1, c0 + a3 - 2.0 * a4 + a7, rref));
-        st.pop(2, encode_pop<FT>(2, c0 + a5 - 2.0 * a6 - a7, rref));
-        st.pop(3, encode_pop<FT>(3, c0 - a3 + 2.0 * a4 + a7, rref));
-        st.pop(4, encode_pop<FT>(4, c0 - a5 + 2.0 * a6 - a7, rref));
-        st.pop(5, encode_pop<FT>(5, cd + a3 + a4 + a5 + a6 + a8, rref));
-        st.pop(6, encode_pop<FT>(6, cd - a3 - a4 + a5 + a6 - a8, rref));
-        st.pop(7, encode_pop<FT>(7, cd - a3 - a4 - a5 - a6 + a8, rref));
-        st.pop(8, encode_pop<FT>(8, cd + a3 + a4 - a5 - a6 - a8, rref));
+        // FP32 storage keeps f* - w_i rho_ref (the deviation) with rho_ref =
+        // rho(t) rounded to FP32, the density stored beside it: w_i rho_ref is
+        // taken off the rest term and the terms common to the axis and to the
+        // diagonal populations.  FP64 storage keeps f* itself.
+        double p0, c0, cd;
+        if constexpr (std::is_same<FT, float>::value) {
+            const double rref = (double)(float)rho;
+            p0 = a0 - 4.0 * a1 + 4.0 * a2 - kW[0] * rref;
+            c0 = a0 - a1 - 2.0 * a2 - kW[1] * rref;
+            cd = a0 + 2.0 * a1 + a2 - kW[5] * rref;
+        } else {
+            p0 = a0 - 4.0 * a1 + 4.0 * a2;
+            c0 = a0 - a1 - 2.0 * a2;       // axis-common part
+            cd = a0 + 2.0 * a1 + a2;       // diagonal-common part
+        }
+        st.pop(0, (FT)p0);
+        st.pop(1, (FT)(c0 + a3 - 2.0 * a4 + a7));
+        st.pop(2, (FT)(c0 + a5 - 2.0 * a6 - a7));
+        st.pop(3, (FT)(c0 - a3 + 2.0 * a4 + a7));
+        st.pop(4, (FT)(c0 - a5 + 2.0 * a6 - a7));
+        st.pop(5, (FT)(cd + a3 + a4 + a5 + a6 + a8));
+        st.pop(6, (FT)(cd - a3 - a4 + a5 + a6 - a8));
+        st.pop(7, (FT)(cd - a3 - a4 - a5 - a6 + a8));
+        st.pop(8, (FT)(cd + a3 + a4 - a5 - a6 - a8));
         st.fields(rho, (FT)vx, (FT)vy);      // rho and v in FP32 with FP32 storage
     }
     return !(rho == rho) || !__builtin_isfinite(vx) || !__builtin_isfinite(vy);
@@ -383,16 +403,17 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
         // copy (tile plus two rings, all inside the fluid since the tile is two
         // nodes from every edge), then the populations and T of this thread's
         // node and of its ring node.
-        constexpr int NQ = (RW * RH + BX * BY - 1) / (BX * BY);
-        float rq[NQ];
+        // thread (tx, ty) copies columns tx + i BX of rows ty + j BY, so the
+        // copy needs no index arithmetic beyond the thread's own position
+        constexpr int NI = (RW + BX - 1) / BX, NJ = (RH + BY - 1) / BY;
+        float rq[NJ][NI];
 #pragma unroll
-        for (int u = 0; u < NQ; ++u) {
-            const int q = threadIdx.x + u * BX * BY;
-            if (q < RW * RH) {
-                const int qx = q % RW, qy = q / RW;
-                rq[u] = rin[(uint32_t)(te.y0 - 2 + qy) * pitch + (uint32_t)(te.x0 - 2 + qx)];
+        for (int j = 0; j < NJ; ++j)
+#pragma unroll
+            for (int i = 0; i < NI; ++i) {
+                const int c = tx + i * BX, r = ty + j * BY;
+                if (c < RW && r < RH) rq[j][i] = rin[(uint32_t)(te.y0 - 2 + r) * pitch + (uint32_t)(te.x0 - 2 + c)];
             }
-        }
         float v[9], vh[9];
         load_inner_raw(fin, plane, pitch, idx, v);
         const double Tn = at_byte(Tt + toff, idx * 8u);
@@ -403,10 +424,12 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
             Th = at_byte(Tt + toff, hidx * 8u);
         }
 #pragma unroll
-        for (int u = 0; u < NQ; ++u) {
-            const int q = threadIdx.x + u * BX * BY;
-            if (q < RW * RH) s_rho[q] = rq[u];
-        }
+        for (int j = 0; j < NJ; ++j)
+#pragma unroll
+            for (int i = 0; i < NI; ++i) {
+                const int c = tx + i * BX, r = ty + j * BY;
+                if (c < RW && r < RH) s_rho[r * RW + c] = rq[j][i];
+            }
         __syncthreads();
         // a block past its loads computes at raised wave priority, so it gets
         // to its stores and frees its slot sooner (0.7 us per launch)
@@ -416,10 +439,9 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
         psi = eos_psi(d, mo.rho, Tn, bad);
         s_psi[(ty + 1) * LW + tx + 1] = psi;
         if (has_h) {
-            double fh[9], rh = 0.0;
+            double fh[9];
             decode_lds<RW>(s_rho, lx + 1, ly + 1, vh, fh);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) rh += fh[i];
+            const double rh = node_rho(fh);
             bool dummy = false;  // errors are flagged by the owning tile
             s_psi[ly * LW + lx] = eos_psi(d, rh, Th, dummy);
         }
@@ -442,12 +464,11 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
             }
             double ph = 0.0;
             if (ok) {
-                double fh[9], rh = 0.0;
+                double fh[9];
                 const uint32_t hidx = (uint32_t)yh * pitch + (uint32_t)xh;
                 if (INNER) pull_inner<FT>(fin, rin, plane, pitch, hidx, fh);
                 else pull_node<FT>(d, fin, rin, xh, yh, pery, fh);
-#pragma unroll
-                for (int i = 0; i < 9; ++i) rh += fh[i];
+                const double rh = node_rho(fh);
                 bool dummy = false;  // errors are flagged by the owning tile
                 ph = eos_psi(d, rh, Tt[toff + hidx], dummy);
             }
@@ -1183,7 +1204,7 @@ __global__ __launch_bounds__(kFluxThreads) void k_flux(const PbDesc *const *__re
 // post-collision values at the source node, so slot (i, y) receives the value
 // node y + e_i will pull, or, when y + e_i is a wall, the value y pulls back
 // as f_opp(i); both buffers are written so frozen-flow runs see the same
-// state on either parity.  rho (FP64, [nyf][pitch] at rsrc) is stored in both
+// state on either parity.  rho (FP64, dense [nyf][nx] at rsrc) is stored in both
 // rho buffers (as FP32 with FP32 storage, the reference of the deviations,
 // which are taken against that stored value); v = 0.
 template <typename FT>
@@ -1195,7 +1216,7 @@ __global__ __launch_bounds__(256) void k_init(const PbDesc *__restrict__ dp, con
     for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < nn; q += (size_t)gridDim.x * blockDim.x) {
         const int y = (int)(q / d.nx), x = (int)(q % d.nx);
         const size_t idx = (size_t)y * d.pitch + x;
-        const double r = rsrc[idx];
+        const double r = rsrc[q];
         const FT rs = (FT)r;
         ((FT *)d.rho[0])[idx] = rs;
         ((FT *)d.rho[1])[idx] = rs;
@@ -1206,7 +1227,7 @@ __global__ __launch_bounds__(256) void k_init(const PbDesc *__restrict__ dp, con
             const int xd = wrap_once(x + kEX[i], d.nx);
             int yd = y + kEY[i];
             if (pery) yd = wrap_once(yd, d.nyf);
-            const double rd = (yd >= 0 && yd < d.nyf) ? rsrc[(size_t)yd * d.pitch + xd] : r;
+            const double rd = (yd >= 0 && yd < d.nyf) ? rsrc[(size_t)yd * d.nx + xd] : r;
             const double fe = kW[i] * rd;
             for (int b = 0; b < 2; ++b) {
                 FT *fo = (FT *)d.f[b];
@@ -1321,6 +1342,34 @@ hipError_t pb_launch_init(int prec, const PbDesc *d_desc, const double *rho_src,
         hipLaunchKernelGGL(k_init<double>, dim3(1024), dim3(256), 0, s, d_desc, rho_src);
     else
         hipLaunchKernelGGL(k_init<float>, dim3(1024), dim3(256), 0, s, d_desc, rho_src);
+    return hipGetLastError();
+}
+
+// rows x width elements from rows spitch elements apart to rows dpitch
+// elements apart (device to device), so that host transfers of pitched arrays
+// are single contiguous copies whatever the row length
+template <typename V>
+__global__ __launch_bounds__(256) void k_repitch(V *__restrict__ dst, size_t dpitch, const V *__restrict__ src,
+                                                 size_t spitch, size_t width, size_t n) {
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
+        const size_t y = q / width, x = q - y * width;
+        dst[y * dpitch + x] = src[y * spitch + x];
+    }
+}
+
+hipError_t pb_launch_repitch(int elem_bytes, void *dst, size_t dpitch, const void *src, size_t spitch, size_t width,
+                             size_t rows, hipStream_t s) {
+    const size_t n = width * rows;
+    if (n == 0) return hipSuccess;
+    const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 8192);
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(k_repitch<double>, dim3(grid), dim3(256), 0, s, (double *)dst, dpitch, (const double *)src,
+                           spitch, width, n);
+    else if (elem_bytes == 4)
+        hipLaunchKernelGGL(k_repitch<float>, dim3(grid), dim3(256), 0, s, (float *)dst, dpitch, (const float *)src,
+                           spitch, width, n);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
