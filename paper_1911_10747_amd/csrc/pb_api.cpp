@@ -376,14 +376,20 @@ int download_rows(pb_domain *d, double *dst, const double *src, int rows, double
     return PB_OK;
 }
 
-// Device memory for the dense rows of an upload (rows x nx doubles), freed
-// when it goes out of scope; none when pitch == nx.
+// Device memory for the dense rows of an upload (rows x nx doubles); none
+// when pitch == nx.  Freed when it goes out of scope, after the domain's
+// stream (whose kernels read it) has drained, on error returns too.
 struct UploadTmp {
     void *p = nullptr;
+    hipStream_t s = nullptr;
     ~UploadTmp() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(p);
+        }
     }
     bool get(const pb_domain *d, int rows) {
+        s = d->stream;
         if (d->pitch == d->cfg.nx) return true;
         return hipMalloc(&p, (size_t)rows * d->cfg.nx * sizeof(double)) == hipSuccess;
     }
