@@ -172,6 +172,21 @@ __device__ __forceinline__ void load_inner_raw(const float PB_GAS *fin, uint32_t
         v[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, boff, 0, 0));
     }
 }
+// load_inner_raw for a node within a row of the fluid whose x neighbours
+// wrap periodically (the tiles at the x edges): the source column of each
+// population is x - 1, x or x + 1 taken modulo nx, per lane
+__device__ __forceinline__ void load_wrap_raw(const float PB_GAS *fin, uint32_t plane, uint32_t pitch, int x, int y,
+                                              int nx, float v[9]) {
+    const uint32_t xm = (uint32_t)wrap_once(x - 1, nx), xp = (uint32_t)wrap_once(x + 1, nx);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const uint32_t xs = kEX[i] == 0 ? (uint32_t)x : (kEX[i] > 0 ? xm : xp);   // x - e_x
+        const uint32_t boff = ((uint32_t)(y - kEY[i]) * pitch + xs) * 4u;
+        const __amdgpu_buffer_rsrc_t r =
+            __builtin_amdgcn_make_buffer_rsrc((void *)(fin + (uint32_t)i * plane), (short)0, -1, 0x00020000);
+        v[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, boff, 0, 0));
+    }
+}
 template <int RW>
 __device__ __forceinline__ void decode_lds(const float *s_rho, int lx, int ly, const float v[9], double f[9]) {
 #pragma unroll
@@ -356,14 +371,22 @@ __device__ __forceinline__ bool node_update(cdesc &d, const double f[9], const M
 }
 
 // ---------------------------------------------------------------- flow step
+// Code paths of a flow tile.  PATH_INNER: every node of the tile and its ring
+// is at least two nodes from the x edges and from the walls.  PATH_XWRAP
+// (FP32 storage): the same two nodes from the walls, a periodic y absent, and
+// x positions taken modulo nx (nx >= BX + 4, so one wrap reaches every
+// position the tile uses).  PATH_GENERAL: any tile.
+enum : int { PATH_GENERAL = 0, PATH_INNER = 1, PATH_XWRAP = 2 };
+
 // One tile: psi over the tile plus a one-node ring in LDS, then forces,
-// velocity and collision on the tile.  INNER: every node of the tile and its
-// ring is at least two nodes from the x edges and from the walls.
-template <typename FT, int BX, int BY, int MODE, bool INNER>
+// velocity and collision on the tile.
+template <typename FT, int BX, int BY, int MODE, int PATH>
 __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, double *s_psi, FT *s_rho,
                                           int *s_bad) {
+    constexpr bool INNER = PATH == PATH_INNER, XWRAP = PATH == PATH_XWRAP;
+    static_assert(!XWRAP || std::is_same<FT, float>::value, "x-wrapped tiles use the FP32 LDS decode");
     constexpr int RW = BX + 4, RH = BY + 4;        // rho(t-1) copy: tile plus two rings
-    constexpr bool RLDS = INNER && std::is_same<FT, float>::value;
+    constexpr bool RLDS = (INNER || XWRAP) && std::is_same<FT, float>::value;
     constexpr int LW = BX + 2, LH = BY + 2;
     constexpr int NHALO = 2 * LW + 2 * BY;
     const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
@@ -401,8 +424,8 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
     if constexpr (RLDS) {
         // Every load of the tile is issued before the first wait: the rho(t-1)
         // copy (tile plus two rings, all inside the fluid since the tile is two
-        // nodes from every edge), then the populations and T of this thread's
-        // node and of its ring node.
+        // nodes from the walls; columns modulo nx on the x-wrapped path), then
+        // the populations and T of this thread's node and of its ring node.
         // thread (tx, ty) copies columns tx + i BX of rows ty + j BY, so the
         // copy needs no index arithmetic beyond the thread's own position
         constexpr int NI = (RW + BX - 1) / BX, NJ = (RH + BY - 1) / BY;
@@ -412,15 +435,19 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
 #pragma unroll
             for (int i = 0; i < NI; ++i) {
                 const int c = tx + i * BX, r = ty + j * BY;
-                if (c < RW && r < RH) rq[j][i] = rin[(uint32_t)(te.y0 - 2 + r) * pitch + (uint32_t)(te.x0 - 2 + c)];
+                const int xc = XWRAP ? wrap_once(te.x0 - 2 + c, d.nx) : te.x0 - 2 + c;
+                if (c < RW && r < RH) rq[j][i] = rin[(uint32_t)(te.y0 - 2 + r) * pitch + (uint32_t)xc];
             }
         float v[9], vh[9];
-        load_inner_raw(fin, plane, pitch, idx, v);
+        if (XWRAP) load_wrap_raw(fin, plane, pitch, xw, yw, d.nx, v);
+        else load_inner_raw(fin, plane, pitch, idx, v);
         const double Tn = at_byte(Tt + toff, idx * 8u);
-        const uint32_t hidx = (uint32_t)(te.y0 + ly - 1) * pitch + (uint32_t)(te.x0 + lx - 1);
+        const int xh = XWRAP ? wrap_once(te.x0 + lx - 1, d.nx) : te.x0 + lx - 1, yh = te.y0 + ly - 1;
+        const uint32_t hidx = (uint32_t)yh * pitch + (uint32_t)xh;
         double Th = 0.0;
         if (has_h) {
-            load_inner_raw(fin, plane, pitch, hidx, vh);
+            if (XWRAP) load_wrap_raw(fin, plane, pitch, xh, yh, d.nx, vh);
+            else load_inner_raw(fin, plane, pitch, hidx, vh);
             Th = at_byte(Tt + toff, hidx * 8u);
         }
 #pragma unroll
@@ -483,7 +510,7 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
             const int yn = yr + kEY[i];
-            const bool wall = !INNER && !pery && (yn < 0 || yn >= d.nyf);
+            const bool wall = PATH == PATH_GENERAL && !pery && (yn < 0 || yn >= d.nyf);
             pn[i] = s_psi[(ty + 1 + kEY[i]) * LW + tx + 1 + kEX[i]];
             gw[i] = 0.0;
             if (wall) {
@@ -514,10 +541,15 @@ void k_flow(const PbDesc *const *__restrict__ dps, const PbTile *__restrict__ ti
         const PbTile te = tiles[tl];
         cdesc &d = *(const PbDesc PB_CAS *)dps[te.dom];
         if (threadIdx.x == 0) s_bad = 0;
-        const bool inner = !(d.flags & F_PERY) && te.x0 >= 2 && te.x0 + BX + 2 <= d.nx && te.y0 >= 2 &&
-                           te.y0 + BY + 2 <= d.nyf;
-        if (inner) flow_tile<FT, BX, BY, MODE, true>(d, te, k, s_psi, s_rho, &s_bad);
-        else flow_tile<FT, BX, BY, MODE, false>(d, te, k, s_psi, s_rho, &s_bad);
+        const bool yin = !(d.flags & F_PERY) && te.y0 >= 2 && te.y0 + BY + 2 <= d.nyf;
+        if (yin && te.x0 >= 2 && te.x0 + BX + 2 <= d.nx) {
+            flow_tile<FT, BX, BY, MODE, PATH_INNER>(d, te, k, s_psi, s_rho, &s_bad);
+        } else if constexpr (std::is_same<FT, float>::value) {
+            if (yin && d.nx >= BX + 4) flow_tile<FT, BX, BY, MODE, PATH_XWRAP>(d, te, k, s_psi, s_rho, &s_bad);
+            else flow_tile<FT, BX, BY, MODE, PATH_GENERAL>(d, te, k, s_psi, s_rho, &s_bad);
+        } else {
+            flow_tile<FT, BX, BY, MODE, PATH_GENERAL>(d, te, k, s_psi, s_rho, &s_bad);
+        }
         __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         if (threadIdx.x == 0 && s_bad) flag_error(d);
