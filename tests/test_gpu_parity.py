@@ -87,6 +87,34 @@ def test_ragged_domain_and_tile_shapes_are_bit_identical(precision):
                 np.testing.assert_array_equal(r[k], ref[k], err_msg=f"{k} differs for tile {tile}")
 
 
+@pytest.mark.parametrize("nx", [67, 68, 69, 132])
+def test_x_edge_tiles_around_the_wrap_limit(nx):
+    """FP32 storage: tiles at the x edges and two rows from the walls take the
+    LDS-decode path with x modulo nx when nx >= tile width + 4, else the
+    general path.  Widths on both sides of that limit for 64- and 128-wide
+    tiles, 80 steps: every tile shape matches the oracle and gives the same
+    bits (the same node by either path)."""
+    P, d, bc, rho, T = pool_case(nx, 40, 3, superheat=0.2, n_spots=3, seed=nx, y0=15)
+    o = oracle_domain(P, bc, rho, T)
+    o.step(80)
+    orr = o.read()
+    ref = None
+    for tile in [(64, 8), (32, 8), (128, 4), (64, 16)]:
+        g = gpu_domain(P, bc, rho, T, 1, tile=tile)
+        g.step(80)
+        g.sync()
+        r = g.read()
+        g.close()
+        errs = compare(r, orr)
+        _report(f"x-edge nx={nx} tile={tile}", errs)
+        assert all(v <= TOL[1] for v in errs.values()), errs
+        if ref is None:
+            ref = r
+        else:
+            for k in ("rho", "ux", "uy", "T", "f"):
+                np.testing.assert_array_equal(r[k], ref[k], err_msg=f"{k} differs for tile {tile}")
+
+
 @pytest.mark.parametrize("precision,nx,nyf,nys", [(0, 3590, 1403, 56), (1, 4096, 1800, 64)])
 def test_short_tail_strips_bit_identical(precision, nx, nyf, nys):
     """Domains with enough 28- or 36-row energy strips that the library ends
