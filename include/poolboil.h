@@ -156,6 +156,19 @@ int pb_thermal_strip_rows(const pb_config *cfg, int *rows);
  * (PB_EINVAL otherwise).  Host only: for tests and tools. */
 int pb_thermal_work_list(const pb_config *const *cfgs, int32_t n, int32_t *out, int64_t cap, int64_t *count);
 
+/* The flow launch's work list of one domain stepped alone (a batch holds the
+ * same tiles for each member, with the first member's tile shape), as (x0,
+ * y0, width, height, alt) quintuples in out[5 * i .. 5 * i + 4]: a tile
+ * covers fluid columns x0 .. x0 + width - 1 and rows y0 .. y0 + height - 1
+ * (clipped to the domain), in the order built before the XCD ordering.
+ * alt = 1 marks a 32 x 16 tile: with FP32-deviation storage and a 512-thread
+ * tile shape wider than 32, the columns past the domain's last full tile go
+ * to such tiles when that takes fewer tiles than partial ones.  *count
+ * receives the number of tiles; out may be NULL to query it, else cap
+ * (quintuples) must hold them (PB_EINVAL otherwise).  Host only: for tests
+ * and tools.  PB_EINVAL for an invalid configuration. */
+int pb_flow_work_list(const pb_config *cfg, int32_t *out, int64_t cap, int64_t *count);
+
 /* Create a domain.  stream: a hipStream_t (NULL = the null stream).  dev_mem:
  * NULL to let the library allocate, or caller-owned device memory of at least
  * pb_domain_bytes() bytes (256-byte aligned) that must outlive the domain.

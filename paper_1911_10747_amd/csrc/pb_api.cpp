@@ -190,6 +190,28 @@ void make_tiles(std::vector<PbTile> &out, int dom, int nx, int ny, int bx, int b
         for (int x0 = 0; x0 < nx; x0 += bx) out.push_back(PbTile{dom, x0, y0, 0});
 }
 
+// Flow tiles of one domain for launches of (precision, variant).  Where the
+// launch takes alternate tiles, the columns past the last full tile go to
+// alternate tiles when that takes fewer of them than the partial tiles would
+// (a partial tile computes as much as a full one); the list is never longer
+// than make_tiles'.  Returns whether it added alternate tiles.
+bool make_flow_tiles(std::vector<PbTile> &out, int dom, int nx, int ny, int prec, int variant) {
+    int bx, by, ax, ay;
+    pb_flow_tile_shape(variant, &bx, &by);
+    const bool alt_ok = pb_flow_alt_shape(prec, variant, &ax, &ay) != 0;
+    const int full = nx / bx * bx, r = nx - full;
+    const bool alt = alt_ok && r > 0 &&
+                     (int64_t)((r + ax - 1) / ax) * ((ny + ay - 1) / ay) < (int64_t)((ny + by - 1) / by);
+    if (!alt) {
+        make_tiles(out, dom, nx, ny, bx, by);
+        return false;
+    }
+    make_tiles(out, dom, full, ny, bx, by);
+    for (int y0 = 0; y0 < ny; y0 += ay)
+        for (int x0 = full; x0 < nx; x0 += ax) out.push_back(PbTile{dom, x0, y0, 1});
+    return true;
+}
+
 // A domain's share of an energy-strip work list: index, columns, thermal rows.
 struct ThermalDom {
     int dom, nx, nr;
@@ -198,7 +220,7 @@ struct ThermalDom {
 // Energy-strip work list of one or more domains (slots: wavefronts the chip
 // holds at once, 256 CUs x 4 SIMDs x the sweep's waves per SIMD).  Strips of
 // by rows; when there are more of them than slots, the top rows of every
-// domain become 8-row strips (short_strip = 1), about 0.6 slots in all,
+// domain become 8-row strips (alt = 1), about 0.6 slots in all,
 // shared out by area, and are placed last: the wavefronts that start last are
 // then short and the launch ends with few idle slots (4096 x 2112 rows, FP32,
 // 28-row strips: 91.5 -> 81.7 us).  With ordered set, each part is ordered for
@@ -275,6 +297,7 @@ struct pb_domain {
     int par = 0;
     bool fields_set = false;
     int fvar = 0, tvar = 0;
+    int flow_launch_var = 0;     // fvar, with PB_FLOW_ALT_TILES if its work list holds alternate tiles
     int nt_flow = 0, nt_th = 0;
     int device = 0;              // the GPU the domain lives on
     PbTile *dtiles_flow = nullptr, *dtiles_th = nullptr;
@@ -288,6 +311,7 @@ struct pb_batch {
     hipStream_t stream = nullptr;
     bool owns_stream = false;
     int prec = 0, fvar = 0, tvar = 0;
+    int flow_launch_var = 0;     // fvar, with PB_FLOW_ALT_TILES if the flow work list holds alternate tiles
     int nt_flow = 0, nt_th = 0, grid_flow = 0, grid_th = 0;
     int spg = 0, persistent = 0;
     // device tables of the launches, one buffer: descriptor pointers, flow
@@ -329,10 +353,9 @@ int upload_desc(pb_domain *d) {
 }
 
 int upload_tiles(pb_domain *d) {
-    int bx, by;
     std::vector<PbTile> tf, tt;
-    pb_flow_tile_shape(d->fvar, &bx, &by);
-    make_tiles(tf, 0, d->cfg.nx, d->cfg.ny_fluid, bx, by);
+    const bool alt = make_flow_tiles(tf, 0, d->cfg.nx, d->cfg.ny_fluid, d->cfg.precision, d->fvar);
+    d->flow_launch_var = d->fvar | (alt ? PB_FLOW_ALT_TILES : 0);
     thermal_list(tt, {&d->cfg}, d->tvar, true);
     xcd_order(tf);
     if ((int)tf.size() > max_tiles(d->cfg.nx, d->cfg.ny_fluid, true) || (int)tt.size() > max_tiles(d->cfg.nx, d->nr, false))
@@ -409,7 +432,7 @@ int enqueue_steps(pb_domain *d, int64_t n) {
     while (n > 0) {
         const int m = (int)std::min<int64_t>(n, chunk);
         for (int k = 0; k < m; ++k) {
-            if (!frozen) PB_HIP(pb_launch_flow(d->cfg.precision, PB_MODE_STEP, d->fvar, dp, d->dtiles_flow, d->nt_flow,
+            if (!frozen) PB_HIP(pb_launch_flow(d->cfg.precision, PB_MODE_STEP, d->flow_launch_var, dp, d->dtiles_flow, d->nt_flow,
                                                d->nt_flow, k, d->stream));
             if (!iso) PB_HIP(pb_launch_thermal(d->cfg.precision, d->tvar, dp, d->dtiles_th, d->nt_th, d->nt_th, k, d->stream));
             const int64_t tk = d->t + k + 1;
@@ -443,6 +466,30 @@ int pb_thermal_strip_rows(const pb_config *cfg, int *rows) {
     return PB_OK;
 }
 
+int pb_flow_work_list(const pb_config *cfg, int32_t *out, int64_t cap, int64_t *count) {
+    if (!count) return fail(PB_EINVAL, "count is NULL");
+    int rc = validate(cfg);
+    if (rc) return rc;
+    const int fvar = flow_variant_of(*cfg);
+    int bx, by, ax, ay;
+    pb_flow_tile_shape(fvar, &bx, &by);
+    pb_flow_alt_shape(cfg->precision, fvar, &ax, &ay);
+    std::vector<PbTile> tf;
+    make_flow_tiles(tf, 0, cfg->nx, cfg->ny_fluid, cfg->precision, fvar);
+    *count = (int64_t)tf.size();
+    if (out && cap < (int64_t)tf.size()) return fail(PB_EINVAL, "out holds %lld tiles, %lld needed", (long long)cap,
+                                                     (long long)tf.size());
+    if (out)
+        for (size_t i = 0; i < tf.size(); ++i) {
+            out[5 * i] = tf[i].x0;
+            out[5 * i + 1] = tf[i].y0;
+            out[5 * i + 2] = tf[i].alt ? ax : bx;
+            out[5 * i + 3] = tf[i].alt ? ay : by;
+            out[5 * i + 4] = tf[i].alt;
+        }
+    return PB_OK;
+}
+
 int pb_thermal_work_list(const pb_config *const *cfgs, int32_t n, int32_t *out, int64_t cap, int64_t *count) {
     if (!cfgs || n < 1) return fail(PB_EINVAL, "need at least one configuration");
     if (!count) return fail(PB_EINVAL, "count is NULL");
@@ -466,7 +513,7 @@ int pb_thermal_work_list(const pb_config *const *cfgs, int32_t n, int32_t *out, 
             out[4 * i] = tt[i].dom;
             out[4 * i + 1] = tt[i].x0;
             out[4 * i + 2] = tt[i].y0;
-            out[4 * i + 3] = tt[i].short_strip ? 8 : by;
+            out[4 * i + 3] = tt[i].alt ? 8 : by;
         }
     return PB_OK;
 }
@@ -762,7 +809,7 @@ int read_through(pb_domain *d, double *stage, double *rho, double *ux, double *u
         if ((rc = upload_desc(d))) return rc;
     }
     if (rho || ux || uy || f) {
-        PB_HIP(pb_launch_flow(d->cfg.precision, PB_MODE_READ, d->fvar, (const PbDesc *const *)d->dptr, d->dtiles_flow,
+        PB_HIP(pb_launch_flow(d->cfg.precision, PB_MODE_READ, d->flow_launch_var, (const PbDesc *const *)d->dptr, d->dtiles_flow,
                               d->nt_flow, d->nt_flow, 0, d->stream));
     }
     if (rho) PB_HIP(hipMemcpyAsync(rho, d->hd.rd_rho, bytes, hipMemcpyDeviceToHost, d->stream));
@@ -870,7 +917,7 @@ int pb_profile_steps(pb_domain *d, int64_t n, double *avg_ms) {
     for (int k = 0; k < m && err == hipSuccess; ++k) {
         err = hipEventRecord(ev[2 * k], d->stream);
         if (err == hipSuccess && !frozen)
-            err = pb_launch_flow(d->cfg.precision, PB_MODE_STEP, d->fvar, dp, d->dtiles_flow, d->nt_flow, d->nt_flow, k,
+            err = pb_launch_flow(d->cfg.precision, PB_MODE_STEP, d->flow_launch_var, dp, d->dtiles_flow, d->nt_flow, d->nt_flow, k,
                                  d->stream);
         if (err == hipSuccess) err = hipEventRecord(ev[2 * k + 1], d->stream);
         if (err == hipSuccess && !iso) err = pb_launch_thermal(d->cfg.precision, d->tvar, dp, d->dtiles_th, d->nt_th, d->nt_th, k, d->stream);
@@ -956,20 +1003,19 @@ int batch_rebuild(pb_batch *b) {
     std::vector<PbTile> tf, tt;
     std::vector<PbDesc *> ptrs(n);
     int prec = b->prec, fvar = b->fvar, tvar = b->tvar;
+    bool flow_alt = false;
     if (n > 0) {
         prec = b->doms[0]->cfg.precision;
         fvar = b->doms[0]->fvar;
         std::vector<const pb_config *> cfgs(n);
         for (int j = 0; j < n; ++j) cfgs[j] = &b->doms[j]->cfg;
         tvar = launch_thermal_variant(cfgs);
-        int fbx, fby;
-        pb_flow_tile_shape(fvar, &fbx, &fby);
         // a launch's work-list holds the tiles of the domains that take that
         // part of the step (frozen-flow domains skip the flow, isothermal ones
         // the energy equation, as when stepped alone)
         for (int j = 0; j < n; ++j) {
             if (!(b->doms[j]->cfg.flags & PB_FROZEN_FLOW))
-                make_tiles(tf, j, b->doms[j]->cfg.nx, b->doms[j]->cfg.ny_fluid, fbx, fby);
+                if (make_flow_tiles(tf, j, b->doms[j]->cfg.nx, b->doms[j]->cfg.ny_fluid, prec, fvar)) flow_alt = true;
             ptrs[j] = b->doms[j]->ddesc;
         }
         thermal_list(tt, cfgs, tvar, b->persistent == 0);
@@ -1018,6 +1064,7 @@ int batch_rebuild(pb_batch *b) {
     b->dtiles_th = (PbTile *)(b->dtab + o_tt);
     b->prec = prec;
     b->fvar = fvar;
+    b->flow_launch_var = fvar | (flow_alt ? PB_FLOW_ALT_TILES : 0);
     b->tvar = tvar;
     b->nt_flow = (int)tf.size();
     b->nt_th = (int)tt.size();
@@ -1138,7 +1185,7 @@ static int batch_enqueue(pb_batch *b, int nsteps, const std::vector<char> &flux)
     const int nd = (int)b->doms.size();
     for (int k = 0; k < nsteps; ++k) {
         if (b->nt_flow > 0)
-            PB_HIP(pb_launch_flow(b->prec, PB_MODE_STEP, b->fvar, dp, b->dtiles_flow, b->nt_flow, b->grid_flow, k,
+            PB_HIP(pb_launch_flow(b->prec, PB_MODE_STEP, b->flow_launch_var, dp, b->dtiles_flow, b->nt_flow, b->grid_flow, k,
                                   b->stream));
         if (b->nt_th > 0)
             PB_HIP(pb_launch_thermal(b->prec, b->tvar, dp, b->dtiles_th, b->nt_th, b->grid_th, k, b->stream));

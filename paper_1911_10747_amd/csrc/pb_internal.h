@@ -49,7 +49,10 @@ struct PbDesc {
 
 struct PbTile {
     int32_t dom, x0, y0;
-    int32_t short_strip;  // energy sweep: 1 = an 8-row strip, whatever the launch's strip height
+    // 1 = the launch's alternate shape: in the energy sweep an 8-row strip,
+    // whatever the launch's strip height; in a 512-thread FP32 flow launch a
+    // 32 x 16 tile (the columns past a domain's last full tile)
+    int32_t alt;
 };
 
 enum { PB_MODE_STEP = 0, PB_MODE_READ = 1 };
@@ -57,6 +60,9 @@ enum { PB_MODE_STEP = 0, PB_MODE_READ = 1 };
 // Launch helpers implemented in pb_kernels.hip.  All return hipError_t.
 // prec: 0 = FP64 storage, 1 = FP32 deviation storage.
 // d_descs is a device array of device pointers to the domains' descriptors.
+// tile_variant may carry PB_FLOW_ALT_TILES: the work list holds alternate
+// tiles (pb_flow_alt_shape), launched with the kernel that handles them.
+#define PB_FLOW_ALT_TILES 0x100
 hipError_t pb_launch_flow(int prec, int mode, int tile_variant, const PbDesc *const *d_descs, const PbTile *d_tiles,
                           int ntiles, int grid, int k, hipStream_t s);
 hipError_t pb_launch_thermal(int prec, int tile_variant, const PbDesc *const *d_descs, const PbTile *d_tiles,
@@ -78,6 +84,9 @@ hipError_t pb_scratch_address(void **ptr, size_t *bytes);
 
 // Tile geometry of the variants (x, y extents of one block's tile).
 void pb_flow_tile_shape(int variant, int *bx, int *by);
+// Whether flow launches of this precision (0 FP64, 1 FP32 deviation) and
+// variant take tiles of the alternate shape (PbTile.alt), and that shape.
+int pb_flow_alt_shape(int prec, int variant, int *ax, int *ay);
 void pb_thermal_tile_shape(int variant, int *bx, int *by);
 int pb_flow_variants();
 int pb_thermal_variants();

@@ -389,7 +389,12 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
     constexpr bool RLDS = (INNER || XWRAP) && std::is_same<FT, float>::value;
     constexpr int LW = BX + 2, LH = BY + 2;
     constexpr int NHALO = 2 * LW + 2 * BY;
-    const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
+    // the thread index through an empty asm, so that what is derived from it
+    // is formed per tile instead of being hoisted out of the tile loop and
+    // held in registers across it
+    int tid = (int)threadIdx.x;
+    __asm__ volatile("" : "+v"(tid));
+    const int tx = tid % BX, ty = tid / BX;
     const bool pery = (d.flags & F_PERY) != 0;
     const int pin = (int)((d.par0 + k) & 1), pout = pin ^ 1;
     const FT PB_GAS *fin = gcast<FT>(d.f[pin]);
@@ -411,10 +416,10 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
     const uint32_t idx = (uint32_t)yw * pitch + (uint32_t)xw;
 
     // ring node of psi around the tile handled by this thread, if any
-    const bool has_h = (int)threadIdx.x < NHALO;
+    const bool has_h = tid < NHALO;
     int lx = 0, ly = 0;
     {
-        const int h = threadIdx.x;
+        const int h = tid;
         if (h < LW) { lx = h; ly = 0; }
         else if (h < 2 * LW) { lx = h - LW; ly = LH - 1; }
         else if (h < 2 * LW + BY) { lx = 0; ly = h - 2 * LW + 1; }
@@ -527,28 +532,51 @@ __device__ __forceinline__ void flow_tile(cdesc &d, const PbTile &te, int k, dou
     }
 }
 
+// One tile of shape TX x TY by the path its position allows.
+template <typename FT, int TX, int TY, int MODE>
+__device__ __forceinline__ void flow_tile_any(cdesc &d, const PbTile &te, int k, double *s_psi, FT *s_rho,
+                                              int *s_bad) {
+    const bool yin = !(d.flags & F_PERY) && te.y0 >= 2 && te.y0 + TY + 2 <= d.nyf;
+    if (yin && te.x0 >= 2 && te.x0 + TX + 2 <= d.nx) {
+        flow_tile<FT, TX, TY, MODE, PATH_INNER>(d, te, k, s_psi, s_rho, s_bad);
+    } else if constexpr (std::is_same<FT, float>::value) {
+        if (yin && d.nx >= TX + 4) flow_tile<FT, TX, TY, MODE, PATH_XWRAP>(d, te, k, s_psi, s_rho, s_bad);
+        else flow_tile<FT, TX, TY, MODE, PATH_GENERAL>(d, te, k, s_psi, s_rho, s_bad);
+    } else {
+        flow_tile<FT, TX, TY, MODE, PATH_GENERAL>(d, te, k, s_psi, s_rho, s_bad);
+    }
+}
+
+// Alternate tile of 512-thread FP32 launches wider than 32: 32 x 16, for the
+// columns past a domain's last full tile (a partial tile computes as much as
+// a full one, so a remainder of 32 columns or fewer costs half as much in
+// 32 x 16 tiles)
+template <typename FT, int BX, int BY>
+constexpr bool kFlowAlt = std::is_same<FT, float>::value && BX * BY == 512 && BX > 32;
+constexpr int kAltX = 32, kAltY = 16;
+
 // 512-thread stepping blocks are held to 80 VGPRs, 6 waves per SIMD (three
-// blocks per CU)
-template <typename FT, int BX, int BY, int MODE>
+// blocks per CU).  ALT: the work list holds alternate tiles (a separate
+// kernel, so that launches without them keep the smaller code)
+template <typename FT, int BX, int BY, int MODE, bool ALT>
 __global__ __launch_bounds__(BX *BY, (BX * BY == 512 && MODE == PB_MODE_STEP ? 6 : 1))
 void k_flow(const PbDesc *const *__restrict__ dps, const PbTile *__restrict__ tiles, int ntiles, int k) {
-    constexpr int LW = BX + 2, LH = BY + 2;
-    static_assert(2 * LW + 2 * BY <= BX * BY, "halo larger than block");
-    __shared__ double s_psi[LW * LH];
-    __shared__ FT s_rho[(BX + 4) * (BY + 4)];
+    static_assert(!ALT || kFlowAlt<FT, BX, BY>, "no alternate tiles for this launch shape");
+    constexpr int NPSI = std::max((BX + 2) * (BY + 2), ALT ? (kAltX + 2) * (kAltY + 2) : 0);
+    constexpr int NRHO = std::max((BX + 4) * (BY + 4), ALT ? (kAltX + 4) * (kAltY + 4) : 0);
+    static_assert(2 * (BX + 2) + 2 * BY <= BX * BY, "halo larger than block");
+    __shared__ double s_psi[NPSI];
+    __shared__ FT s_rho[NRHO];
     __shared__ int s_bad;
     for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
         const PbTile te = tiles[tl];
         cdesc &d = *(const PbDesc PB_CAS *)dps[te.dom];
         if (threadIdx.x == 0) s_bad = 0;
-        const bool yin = !(d.flags & F_PERY) && te.y0 >= 2 && te.y0 + BY + 2 <= d.nyf;
-        if (yin && te.x0 >= 2 && te.x0 + BX + 2 <= d.nx) {
-            flow_tile<FT, BX, BY, MODE, PATH_INNER>(d, te, k, s_psi, s_rho, &s_bad);
-        } else if constexpr (std::is_same<FT, float>::value) {
-            if (yin && d.nx >= BX + 4) flow_tile<FT, BX, BY, MODE, PATH_XWRAP>(d, te, k, s_psi, s_rho, &s_bad);
-            else flow_tile<FT, BX, BY, MODE, PATH_GENERAL>(d, te, k, s_psi, s_rho, &s_bad);
+        if constexpr (ALT) {
+            if (te.alt) flow_tile_any<FT, kAltX, kAltY, MODE>(d, te, k, s_psi, s_rho, &s_bad);
+            else flow_tile_any<FT, BX, BY, MODE>(d, te, k, s_psi, s_rho, &s_bad);
         } else {
-            flow_tile<FT, BX, BY, MODE, PATH_GENERAL>(d, te, k, s_psi, s_rho, &s_bad);
+            flow_tile_any<FT, BX, BY, MODE>(d, te, k, s_psi, s_rho, &s_bad);
         }
         __builtin_amdgcn_s_setprio(0);
         __syncthreads();
@@ -1153,7 +1181,7 @@ __device__ __forceinline__ void thermal_tile(cdesc &d, const PbTile &te, int k, 
     }
 }
 
-// A tile with short_strip set is an 8-row strip: the work-list ends with such strips
+// A tile with alt set is an 8-row strip: the work-list ends with such strips
 // so that the last wavefronts to start are short ones.
 template <typename VT, int H, int WPE, int UNR>
 __global__ __launch_bounds__(64, WPE) void k_thermal_sweep(const PbDesc *const *__restrict__ dps,
@@ -1162,7 +1190,7 @@ __global__ __launch_bounds__(64, WPE) void k_thermal_sweep(const PbDesc *const *
     for (int tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
         const PbTile te = tiles[tl];
         cdesc &d = *(const PbDesc PB_CAS *)dps[te.dom];
-        if (te.short_strip) thermal_tile<VT, 8, 16>(d, te, k, lane);
+        if (te.alt) thermal_tile<VT, 8, 16>(d, te, k, lane);
         else thermal_tile<VT, H, UNR>(d, te, k, lane);
     }
 }
@@ -1299,19 +1327,40 @@ void pb_flow_tile_shape(int v, int *bx, int *by) {
     *bx = kFlowShapes[v][0];
     *by = kFlowShapes[v][1];
 }
+int pb_flow_alt_shape(int prec, int v, int *ax, int *ay) {
+    *ax = kAltX;
+    *ay = kAltY;
+    const int bx = kFlowShapes[v][0], by = kFlowShapes[v][1];
+    return prec == 1 && bx * by == 512 && bx > kAltX;
+}
 void pb_thermal_tile_shape(int v, int *bx, int *by) {
     *bx = kThermalShapes[v][0];
     *by = kThermalShapes[v][1];
 }
 
+template <typename FT, int BX, int BY, int MODE>
+static hipError_t launch_flow_shape(bool alt, const PbDesc *const *dps, const PbTile *t, int nt, int grid, int k,
+                                    hipStream_t s) {
+    if constexpr (kFlowAlt<FT, BX, BY>) {
+        if (alt) {
+            hipLaunchKernelGGL((k_flow<FT, BX, BY, MODE, true>), dim3(grid), dim3(BX * BY), 0, s, dps, t, nt, k);
+            return hipGetLastError();
+        }
+    } else {
+        if (alt) return hipErrorInvalidValue;   // this shape has no alternate tiles
+    }
+    hipLaunchKernelGGL((k_flow<FT, BX, BY, MODE, false>), dim3(grid), dim3(BX * BY), 0, s, dps, t, nt, k);
+    return hipGetLastError();
+}
+
 template <typename FT, int MODE>
 static hipError_t launch_flow_t(int variant, const PbDesc *const *dps, const PbTile *t, int nt, int grid, int k,
                                 hipStream_t s) {
-    switch (variant) {
-#define PB_FLOW_CASE(V, BX, BY)                                                                       \
-    case V:                                                                                          \
-        hipLaunchKernelGGL((k_flow<FT, BX, BY, MODE>), dim3(grid), dim3(BX * BY), 0, s, dps, t, nt, k); \
-        break;
+    const bool alt = (variant & PB_FLOW_ALT_TILES) != 0;
+    switch (variant & ~PB_FLOW_ALT_TILES) {
+#define PB_FLOW_CASE(V, BX, BY) \
+    case V:                    \
+        return launch_flow_shape<FT, BX, BY, MODE>(alt, dps, t, nt, grid, k, s);
         PB_FLOW_CASE(0, 64, 4)
         PB_FLOW_CASE(1, 64, 8)
         PB_FLOW_CASE(2, 32, 8)
@@ -1322,7 +1371,6 @@ static hipError_t launch_flow_t(int variant, const PbDesc *const *dps, const PbT
         default:
             return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t pb_launch_flow(int prec, int mode, int variant, const PbDesc *const *d_descs, const PbTile *d_tiles, int ntiles,

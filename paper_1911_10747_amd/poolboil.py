@@ -18,7 +18,7 @@ PB_FP64, PB_FP32_DEV = 0, 1
 PB_PERIODIC_Y, PB_ISOTHERMAL, PB_FROZEN_FLOW, PB_SBAR2_PLUS, PB_VARPI_FM_ONLY = 0x1, 0x2, 0x4, 0x8, 0x10
 
 EXPORTED = [
-    "pb_domain_bytes", "pb_thermal_strip_rows", "pb_thermal_work_list", "pb_create_domain", "pb_destroy_domain", "pb_set_bc", "pb_set_fields", "pb_set_fields_full",
+    "pb_domain_bytes", "pb_thermal_strip_rows", "pb_thermal_work_list", "pb_flow_work_list", "pb_create_domain", "pb_destroy_domain", "pb_set_bc", "pb_set_fields", "pb_set_fields_full",
     "pb_step", "pb_sync", "pb_read_fields", "pb_read_fields_noalloc", "pb_flux_window", "pb_heat_flux", "pb_profile_steps", "pb_profile_reserve", "pb_time",
     "pb_rho_bar",
     "pb_batch_create", "pb_batch_step", "pb_batch_destroy", "pb_batch_add", "pb_batch_remove", "pb_batch_size", "pb_eos_critical_temperature", "pb_eos_coexistence",
@@ -83,6 +83,7 @@ def _load():
         "pb_thermal_strip_rows": ([C.POINTER(Config), C.POINTER(C.c_int)], C.c_int),
         "pb_thermal_work_list": ([C.POINTER(C.POINTER(Config)), C.c_int32, C.POINTER(C.c_int32), C.c_int64,
                                   C.POINTER(C.c_int64)], C.c_int),
+        "pb_flow_work_list": ([C.POINTER(Config), C.POINTER(C.c_int32), C.c_int64, C.POINTER(C.c_int64)], C.c_int),
         "pb_create_domain": ([C.POINTER(Config), vp, vp, C.c_size_t, C.POINTER(vp)], C.c_int),
         "pb_destroy_domain": ([vp], None),
         "pb_set_bc": ([vp, C.POINTER(BC)], C.c_int),
@@ -170,6 +171,17 @@ def thermal_work_list(cfgs):
     _check(lib.pb_thermal_work_list(arr, len(cfgs), None, 0, C.byref(n)))
     out = np.zeros((n.value, 4), dtype=np.int32)
     _check(lib.pb_thermal_work_list(arr, len(cfgs), out.ctypes.data_as(C.POINTER(C.c_int32)), n.value, C.byref(n)))
+    return out
+
+
+def flow_work_list(cfg):
+    """The flow launch's tiles of one domain: int32 array of (x0, y0, width,
+    height, alt) rows."""
+    import numpy as np
+    n = C.c_int64()
+    _check(lib.pb_flow_work_list(C.byref(cfg), None, 0, C.byref(n)))
+    out = np.zeros((n.value, 5), dtype=np.int32)
+    _check(lib.pb_flow_work_list(C.byref(cfg), out.ctypes.data_as(C.POINTER(C.c_int32)), n.value, C.byref(n)))
     return out
 
 

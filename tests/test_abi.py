@@ -158,6 +158,46 @@ def test_energy_work_list_ends_with_short_strips():
         pb.thermal_work_list([six[0], cfg(nx=100, ny_fluid=100, ny_solid=10, precision=0)])
 
 
+def test_flow_work_list_covers_each_node_once():
+    """The flow launch's tiles of one domain (host only): every fluid node is
+    in exactly one tile (tiles clipped to the domain); with FP32 storage and
+    64x8 or 128x4 tiles the columns past the last full tile go to 32x16
+    tiles when that takes fewer tiles, and the list is never longer than
+    full-shape tiles over the whole domain; FP64 storage and other shapes
+    take no alternate tiles."""
+    from paper_1911_10747_amd import poolboil as pb
+    P = dict(W.BASE_PARAMS, Tc=0.07, rho_L=6.5, rho_V=0.38, rho_S=19.5)
+    cfg = lambda **kw: pb.make_config(**dict(P, **kw))
+
+    def cover(w, nx, ny):
+        grid = np.zeros((ny, nx), dtype=np.int32)
+        for x0, y0, bw, bh, alt in w:
+            assert 0 <= x0 < nx and 0 <= y0 < ny
+            grid[y0:y0 + bh, x0:x0 + bw] += 1
+        assert (grid == 1).all(), np.unique(grid)
+
+    for prec, tile, nx, ny, n_alt in [
+            (1, (64, 8), 77, 45, 3),       # 13 columns past 64: 3 tiles of 32x16 instead of 6 of 64x8
+            (1, (64, 8), 132, 40, 3),      # 4 columns past 128
+            (1, (64, 8), 100, 40, 0),      # 36 columns past 64: more than 32, no alternate tiles
+            (1, (64, 8), 4096, 2048, 0),   # no columns past the last full tile
+            (1, (64, 8), 70, 3, 0),        # one row: a 32x16 tile saves nothing
+            (1, (128, 4), 200, 64, 12),    # 72 columns past 128: 3 x 4 tiles of 32x16 instead of 16 of 128x4
+            (1, (32, 16), 77, 45, 0),      # a 32-wide shape has no alternate shape
+            (1, (64, 4), 77, 45, 0),       # 256 threads
+            (0, (64, 8), 77, 45, 0)]:      # FP64 storage
+        c = cfg(nx=nx, ny_fluid=ny, ny_solid=3, precision=prec, tile_x=tile[0], tile_y=tile[1])
+        w = pb.flow_work_list(c)
+        cover(w, nx, ny)
+        alt = w[w[:, 4] == 1]
+        assert len(alt) == n_alt, (tile, nx, ny, len(alt))
+        assert (alt[:, 2] == 32).all() and (alt[:, 3] == 16).all()
+        assert (w[w[:, 4] == 0][:, 2:4] == tile).all()
+        assert len(w) <= -(-nx // tile[0]) * -(-ny // tile[1])
+        if n_alt:
+            assert alt[:, 0].min() == nx // tile[0] * tile[0]
+
+
 def test_null_handles_refused_without_gpu():
     """The batch-membership calls and the allocation-free read check their
     handles on the host before any device work."""
