@@ -555,11 +555,12 @@ template <typename FT, int BX, int BY>
 constexpr bool kFlowAlt = std::is_same<FT, float>::value && BX * BY == 512 && BX > 32;
 constexpr int kAltX = 32, kAltY = 16;
 
-// 512-thread stepping blocks are held to 80 VGPRs, 6 waves per SIMD (three
-// blocks per CU).  ALT: the work list holds alternate tiles (a separate
-// kernel, so that launches without them keep the smaller code)
+// 512-thread stepping blocks are held to 80 VGPRs with FP32 storage, 6
+// waves per SIMD (three blocks per CU), and to 64 with FP64 storage, 8 waves
+// per SIMD (four blocks per CU).  ALT: the work list holds alternate tiles (a
+// separate kernel, so that launches without them keep the smaller code)
 template <typename FT, int BX, int BY, int MODE, bool ALT>
-__global__ __launch_bounds__(BX *BY, (BX * BY == 512 && MODE == PB_MODE_STEP ? 6 : 1))
+__global__ __launch_bounds__(BX *BY, (BX * BY == 512 && MODE == PB_MODE_STEP ? (sizeof(FT) == 8 ? 8 : 6) : 1))
 void k_flow(const PbDesc *const *__restrict__ dps, const PbTile *__restrict__ tiles, int ntiles, int k) {
     static_assert(!ALT || kFlowAlt<FT, BX, BY>, "no alternate tiles for this launch shape");
     constexpr int NPSI = std::max((BX + 2) * (BY + 2), ALT ? (kAltX + 2) * (kAltY + 2) : 0);
